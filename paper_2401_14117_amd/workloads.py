@@ -1,0 +1,104 @@
+"""Seeded synthetic workloads (FP64 values plus special-value masks).
+
+This module only draws random numbers; it contains none of the posit
+arithmetic.  Both the GPU path (through the library's own FP64 -> posit
+conversion) and the CPU oracle (through its own conversion) consume what it
+returns, so the two sides see the same inputs without sharing any code.
+
+Workload recipes (all draws use ``numpy.random.default_rng(seed)`` in the order
+listed, row-major):
+
+* ``gemm_uniform``: A (m x k), B (k x n), C (m x n), each ``uniform(-1, 1)``.
+  At m = n = k = 128, seed 1, this is the small Rgemm case.
+* ``gemm_scaled``: each of A, B, C in turn draws U = uniform(-1, 1),
+  S = integers(-12, 12, inclusive), X = U * 2^S, then M = random() < 1e-6 and
+  Z = random() < 0.5; entries with M & Z become 0 and entries with M & ~Z
+  become NaR after conversion.  Square sizes use seed 2000 + n with
+  alpha = beta = 1; the trailing-update shapes m = n = 8192 - 256 j, k = 256
+  use seed 3000 + j with alpha = -1, beta = 1.
+* ``gemm_normal``: normal(0, sigma) entries, the paper's GEMM inputs
+  (Section 4.3); used for the magnitude sweep.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Matrix:
+    values: np.ndarray                      # float64, row-major
+    zero_mask: np.ndarray | None = None     # entries forced to posit 0
+    nar_mask: np.ndarray | None = None      # entries forced to NaR
+
+
+@dataclass
+class GemmCase:
+    name: str
+    m: int
+    n: int
+    k: int
+    alpha: float
+    beta: float
+    A: Matrix
+    B: Matrix
+    C: Matrix
+    meta: dict = field(default_factory=dict)
+
+
+def _scaled(rng, shape, smin=-12, smax=12, sprinkle=1e-6) -> Matrix:
+    u = rng.uniform(-1.0, 1.0, shape)
+    s = rng.integers(smin, smax, size=shape, endpoint=True)
+    x = np.ldexp(u, s.astype(np.int32))      # exact: scaling by a power of 2
+    m = rng.random(shape) < sprinkle
+    z = rng.random(shape) < 0.5
+    return Matrix(x, m & z, m & ~z)
+
+
+def gemm_uniform(m=128, n=128, k=128, seed=1) -> GemmCase:
+    rng = np.random.default_rng(seed)
+    A = Matrix(rng.uniform(-1.0, 1.0, (m, k)))
+    B = Matrix(rng.uniform(-1.0, 1.0, (k, n)))
+    C = Matrix(rng.uniform(-1.0, 1.0, (m, n)))
+    return GemmCase(f"uniform_m{m}_n{n}_k{k}_seed{seed}", m, n, k, 1.0, 1.0, A, B, C)
+
+
+def gemm_scaled(m, n, k, seed, alpha=1.0, beta=1.0, sprinkle=1e-6) -> GemmCase:
+    rng = np.random.default_rng(seed)
+    A = _scaled(rng, (m, k), sprinkle=sprinkle)
+    B = _scaled(rng, (k, n), sprinkle=sprinkle)
+    C = _scaled(rng, (m, n), sprinkle=sprinkle)
+    return GemmCase(f"scaled_m{m}_n{n}_k{k}_seed{seed}", m, n, k, alpha, beta, A, B, C)
+
+
+def gemm_square(n: int) -> GemmCase:
+    """Square sweep case n in {1024, 2048, 4096, 8192}: seed 2000 + n."""
+    c = gemm_scaled(n, n, n, 2000 + n)
+    c.name = f"square_n{n}"
+    return c
+
+
+def gemm_trailing(j: int, N: int = 8192, kb: int = 256) -> GemmCase:
+    """Trailing-update shape m = n = N - kb*j, k = kb: seed 3000 + j."""
+    mn = N - kb * j
+    c = gemm_scaled(mn, mn, kb, 3000 + j, alpha=-1.0, beta=1.0)
+    c.name = f"trailing_j{j}_m{mn}_k{kb}"
+    return c
+
+
+def gemm_normal(n: int, sigma: float, seed: int = 77) -> GemmCase:
+    rng = np.random.default_rng(seed)
+    A = Matrix(rng.normal(0.0, sigma, (n, n)))
+    B = Matrix(rng.normal(0.0, sigma, (n, n)))
+    C = Matrix(rng.normal(0.0, sigma, (n, n)))
+    return GemmCase(f"normal_n{n}_sigma{sigma:g}", n, n, n, 1.0, 1.0, A, B, C)
+
+
+def apply_masks(patterns: np.ndarray, mat: Matrix) -> np.ndarray:
+    """Set the sprinkled special values on an array of posit32 patterns."""
+    if mat.zero_mask is not None:
+        patterns[mat.zero_mask] = 0
+    if mat.nar_mask is not None:
+        patterns[mat.nar_mask] = 0x80000000
+    return patterns

@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the Posit(32,2) Rgemm hot path on one MI355X.
+
+One step = one C = alpha*A*B + beta*C call of the HIP library (posit32_gemm)
+over the whole synthetic workload, inputs already resident in HBM.  The
+default workload is the square n = 8192 case of the Rgemm sweep (magnitudes
+uniform[-1,1] * 2^s, s in [-12,12], NaR/zero sprinkle 1e-6, alpha = beta = 1).
+
+Prints ONE JSON line with the metric, the roofline of the Rgemm kernel
+(integer-VALU bound) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12   # int32 VALU lane-ops/s: CUs x lanes x clock
+PKG = os.path.join(ROOT, "paper_2401_14117_amd")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("p32_device.hpp", "p32_gemm.hip"):
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_valu_per_madd() -> float | None:
+    """Fast-path VALU instructions per multiply-add of the built kernel, counted
+    from its ISA when the library was built."""
+    path = os.path.join(PKG, "libposit32.isa.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        info = json.load(f)
+    if info.get("kernel_hash") != kernel_source_hash():
+        return None
+    return float(info["valu_per_madd"])
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "gemm_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        info = json.load(f)
+    rec = info.get(workload)
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_case(name: str):
+    from paper_2401_14117_amd import workloads as W
+    if name.startswith("square_n"):
+        return W.gemm_square(int(name[len("square_n"):]))
+    if name.startswith("trailing_j"):
+        return W.gemm_trailing(int(name[len("trailing_j"):]))
+    if name.startswith("uniform_n"):
+        n = int(name[len("uniform_n"):])
+        return W.gemm_uniform(n, n, n, seed=1)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def to_device_patterns(mat, dev):
+    """FP64 values -> Posit(32,2) patterns with the library's own conversion;
+    the sprinkled special values are then set by index."""
+    import torch
+    from paper_2401_14117_amd import posit32
+    x = torch.from_numpy(np.ascontiguousarray(mat.values)).to(dev)
+    p = posit32.from_f64(x)
+    del x
+    if mat.zero_mask is not None and mat.zero_mask.any():
+        p[torch.from_numpy(mat.zero_mask).to(dev)] = 0
+    if mat.nar_mask is not None and mat.nar_mask.any():
+        p[torch.from_numpy(mat.nar_mask).to(dev)] = np.int32(-2 ** 31)
+    return p
+
+
+def run_cpu_baseline(case, budget_s: float):
+    import oracle
+    from paper_2401_14117_amd import workloads as W
+    A = W.apply_masks(oracle.vec_from_double(case.A.values), case.A)
+    B = W.apply_masks(oracle.vec_from_double(case.B.values), case.B)
+    C = W.apply_masks(oracle.vec_from_double(case.C.values), case.C)
+    al, be = oracle.from_double(case.alpha), oracle.from_double(case.beta)
+    rng = np.random.default_rng(1234)
+    threads = oracle.num_threads()
+    # calibrate on a small sample, then size the sample to about budget_s
+    count = max(threads, 16)
+    t_cal = 0.0
+    while True:
+        rows = rng.integers(0, case.m, count)
+        cols = rng.integers(0, case.n, count)
+        t0 = time.perf_counter()
+        oracle.gemm_entries(A, B, rows, cols, C[rows, cols], al, be)
+        t_cal = time.perf_counter() - t0
+        if t_cal > 0.5 or count >= case.m * case.n:
+            break
+        count *= 4
+    per_entry = t_cal / count
+    count = int(min(max(budget_s / per_entry, count), case.m * case.n))
+    rows = rng.integers(0, case.m, count)
+    cols = rng.integers(0, case.n, count)
+    t0 = time.perf_counter()
+    oracle.gemm_entries(A, B, rows, cols, C[rows, cols], al, be)
+    dt = time.perf_counter() - t0
+    gpops = 2.0 * count * case.k / dt / 1e9
+    return {"value": round(gpops, 6), "unit": "Gpops/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} sampled C entries of {case.name} (each a full k={case.k} "
+                      f"posit dot product plus alpha/beta epilogue), {dt:.1f} s on "
+                      f"{threads} OpenMP threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="square_n8192")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy (for HBM counter scaling) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU Rgemm is a design "
+              "(row blocks of C per GPU, one broadcast of B) and is not implemented",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2401_14117_amd import posit32
+    posit32.lib()
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        x = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return 0
+
+    case = make_case(args.workload)
+    t0 = time.perf_counter()
+    A = to_device_patterns(case.A, dev)
+    B = to_device_patterns(case.B, dev)
+    C0 = to_device_patterns(case.C, dev)
+    # alpha/beta patterns through the library conversion as well
+    ab = posit32.from_f64(torch.tensor([case.alpha, case.beta], dtype=torch.float64, device=dev))
+    alpha, beta = (int(v) & 0xFFFFFFFF for v in ab.cpu().tolist())
+    C = torch.empty_like(C0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    stream = torch.cuda.current_stream()
+
+    def step(ev0=None, ev1=None):
+        C.copy_(C0)
+        if ev0 is not None:
+            ev0.record(stream)
+        posit32.gemm(A, B, C, alpha, beta)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+
+    m, n, k = case.m, case.n, case.k
+    madds = m * n * k
+    ms_per_step = wall * 1e3 / args.steps
+    gpops = 2.0 * madds / (ms_per_step * 1e-3) / 1e9
+    kavg = float(np.mean(kernel_ms))
+
+    valu = load_valu_per_madd()
+    roof = {"bound": "alu", "achieved": None, "peak": round(PEAK_INT_TOPS, 2),
+            "unit": "Tlane-op/s", "frac": None, "traffic": load_traffic(args.workload),
+            "kernel_ms": round(kavg, 3), "valu_per_madd": valu,
+            "kernel_gpops": round(2.0 * madds / (kavg * 1e-3) / 1e9, 2)}
+    if valu is not None:
+        achieved = valu * madds / (kavg * 1e-3) / 1e12
+        roof["achieved"] = round(achieved, 3)
+        roof["frac"] = round(achieved / PEAK_INT_TOPS, 4)
+
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = run_cpu_baseline(case, args.cpu_budget)
+
+    out = {
+        "metric": "Posit32 Rgemm Gpops/s at n=8192 (% int-VALU peak)",
+        "value": round(gpops, 2),
+        "unit": "Gpops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "posit32 (int32 VALU)",
+        "data": "synthetic",
+        "config": {"workload": case.name, "m": m, "n": n, "k": k,
+                   "alpha": case.alpha, "beta": case.beta,
+                   "inputs": "uniform[-1,1]*2^s, s in [-12,12], NaR/0 sprinkle 1e-6"
+                   if "square" in case.name or "trailing" in case.name else "uniform[-1,1]",
+                   "setup_s": round(setup_s, 2)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,111 @@
+/*
+ * posit32.h -- C ABI of libposit32.so, Posit(32,2) dense linear algebra on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Number format: Posit(32,2) (paper, Section 2, Eq. (1)):
+ *   x = (-1)^s * 16^k * 2^e * 1.f,
+ * a 32-bit pattern holding the sign, a regime run of m identical bits closed by
+ * the opposite bit (k = m-1 for ones, k = -m for zeros), two exponent bits and
+ * 28 - m fraction bits.  0x00000000 is zero, 0x80000000 is NaR, 0x40000000 is
+ * 1.0, 0x7FFFFFFF is maxpos = 2^120, 0x00000001 is minpos = 2^-120, and a
+ * negative value is the two's complement of the pattern of its magnitude.
+ * Every operation returns the exact result rounded once to the nearest posit,
+ * ties to the even pattern, never to 0 or NaR (|x| >= maxpos gives maxpos,
+ * 0 < |x| <= minpos gives minpos).  NaR in any operand gives NaR.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are raw posit patterns (uint32_t), ROW-MAJOR, with a leading
+ *     dimension (row stride, in elements) >= the row width.
+ *   - All matrix and vector pointers are DEVICE pointers owned by the caller
+ *     (e.g. torch int32 tensors); the library never frees or retains them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls enqueue work on that stream and return without synchronising;
+ *     a return of 0 means "enqueued".
+ *   - Arguments are validated on the host before anything is launched.  A
+ *     negative return -i means "argument i (1-based, counting stream as 1)
+ *     is invalid" and nothing was launched.  P32_E_HIP - e (e > 0, a
+ *     hipError_t) reports a HIP runtime failure at launch.
+ *   - Calls that overlap on one stream are ordered; the library keeps no
+ *     global mutable state, so calls on different streams may run
+ *     concurrently on disjoint outputs.
+ */
+#ifndef POSIT32_H
+#define POSIT32_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef uint32_t posit32_t;
+
+enum { P32_NOTRANS = 0, P32_TRANS = 1 };
+
+#define P32_OK 0
+#define P32_E_HIP (-1000)           /* P32_E_HIP - hipError_t */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int posit32_version(void);
+
+/* Human-readable text for a return code (static storage). */
+const char* posit32_strerror(int code);
+
+/*
+ * posit32_gemm -- C = alpha * op(A) * op(B) + beta * C   (paper, Section 3,
+ * Eq. (2), the Level-3 BLAS GEMM interface; the four transpose combinations
+ * of Section 3.2).
+ *
+ *   transa, transb  P32_NOTRANS: op(X) = X;  P32_TRANS: op(X) = X^T.
+ *   m, n, k         op(A) is m x k, op(B) is k x n, C is m x n; each >= 0.
+ *   A, lda          op(A) = A: A is m x k with lda >= max(1, k);
+ *                   op(A) = A^T: A is k x m with lda >= max(1, m).
+ *   B, ldb          op(B) = B: B is k x n with ldb >= max(1, n);
+ *                   op(B) = B^T: B is n x k with ldb >= max(1, k).
+ *   C, ldc          m x n, ldc >= max(1, n); read (unless beta == 0) and
+ *                   written.  C must not alias A or B.
+ *
+ * Order of operations (the result is unique and bit-reproducible):
+ *   for each (i, j):  acc = 0;
+ *                     for p = 0, 1, ..., k-1:  acc = rnd(acc + rnd(a_ip * b_pj));
+ *                     r = rnd(alpha * acc);
+ *                     C_ij = (beta == 0) ? r : rnd(r + rnd(beta * C_ij)).
+ *   alpha == 0 or k == 0: C_ij = (beta == 0) ? 0 : rnd(beta * C_ij); A and B
+ *   are not read.  beta == 0: C is not read (a NaR there is overwritten).
+ *   m == 0 or n == 0: nothing is done.
+ * Errors: -2/-3 bad trans flag, -4/-5/-6 negative m/n/k, -8/-9 null A or bad
+ * lda, -10/-11 null B or bad ldb, -13/-14 null C or bad ldc, -13 also when C
+ * aliases A or B (same base pointer).
+ */
+int posit32_gemm(void* stream, int transa, int transb, int64_t m, int64_t n,
+                 int64_t k, posit32_t alpha, const posit32_t* A, int64_t lda,
+                 const posit32_t* B, int64_t ldb, posit32_t beta, posit32_t* C,
+                 int64_t ldc);
+
+/*
+ * Conversions between binary64 and Posit(32,2) (Section 2, Eq. (1)).
+ *   posit32_from_f64: out[i] = rnd(x[i]); NaN and +-Inf give NaR, +-0 gives 0.
+ *   posit32_to_f64:   out[i] = exact value of p[i]; NaR gives a quiet NaN.
+ * n >= 0; x, p, out are device arrays of n elements.  Errors: -2 n < 0,
+ * -3/-4 null array with n > 0.
+ */
+int posit32_from_f64(void* stream, int64_t n, const double* x, posit32_t* out);
+int posit32_to_f64(void* stream, int64_t n, const posit32_t* p, double* out);
+
+/*
+ * Elementwise arithmetic on device arrays of n elements (the paper's Add,
+ * Mul, Div and Sqrt kernels, Section 4.2, Table 2):
+ *   op P32_OP_ADD: out = rnd(a + b)      P32_OP_SUB: out = rnd(a - b)
+ *   op P32_OP_MUL: out = rnd(a * b)      P32_OP_DIV: out = rnd(a / b), x/0 = NaR
+ *   op P32_OP_SQRT: out = rnd(sqrt(a)), b ignored (may be NULL); sqrt of a
+ *   negative value is NaR.
+ * out may alias a or b.  Errors: -2 bad op, -3 n < 0, -4/-5/-6 null array.
+ */
+enum { P32_OP_ADD = 0, P32_OP_SUB = 1, P32_OP_MUL = 2, P32_OP_DIV = 3, P32_OP_SQRT = 4 };
+int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
+                        const posit32_t* b, posit32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POSIT32_H */

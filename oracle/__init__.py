@@ -80,6 +80,14 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
+def _ld(a: np.ndarray) -> int:
+    """Row stride in elements of a row-major 2-D array (unit column stride)."""
+    if a.size == 0:
+        return max(1, a.shape[1])
+    assert a.strides[1] == 4, "matrices must have unit column stride"
+    return a.strides[0] // 4
+
+
 # ---- scalar operations -------------------------------------------------------
 
 def add(a: int, b: int, N: int = 32) -> int:
@@ -168,8 +176,7 @@ def gemm(A, B, C, alpha: int = ONE32, beta: int = ONE32, transa: bool = False,
         k = A.shape[0] if transa else A.shape[1]
     if n is None:
         n = B.shape[0] if transb else B.shape[1]
-    assert A.strides[1] == 4 and B.strides[1] == 4
-    lda, ldb = A.strides[0] // 4, B.strides[0] // 4
+    lda, ldb = _ld(A), _ld(B)
     lib().oracle_gemm(int(transa), int(transb), m, n, k, alpha, A.ctypes.data, lda,
                       B.ctypes.data, ldb, beta, Cout.ctypes.data, Cout.shape[1])
     return Cout
@@ -187,7 +194,7 @@ def gemm_entries(A, B, rows, cols, Cin, alpha: int = ONE32, beta: int = ONE32,
         k = A.shape[0] if transa else A.shape[1]
     out = np.empty(rows.shape, dtype=np.uint32)
     lib().oracle_gemm_entries(int(transa), int(transb), k, alpha, A.ctypes.data,
-                              A.strides[0] // 4, B.ctypes.data, B.strides[0] // 4, beta,
+                              _ld(A), B.ctypes.data, _ld(B), beta,
                               rows.size, _ptr(rows), _ptr(cols), _ptr(Cin), _ptr(out))
     return out
 

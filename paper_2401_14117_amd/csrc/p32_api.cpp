@@ -1,0 +1,68 @@
+// p32_api.cpp -- the extern "C" boundary of libposit32.so (include/posit32.h):
+// host-side argument validation, then a stream-ordered launch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/posit32.h"
+#include "p32_launch.hpp"
+
+extern "C" {
+
+int posit32_version(void) { return 100; }
+
+const char* posit32_strerror(int code) {
+  if (code == 0) return "ok";
+  if (code <= P32_E_HIP) return hipGetErrorString((hipError_t)(P32_E_HIP - code));
+  if (code < 0) return "invalid argument (the return value is minus its 1-based position)";
+  return "unknown status";
+}
+
+int posit32_gemm(void* stream, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                 posit32_t alpha, const posit32_t* A, int64_t lda, const posit32_t* B,
+                 int64_t ldb, posit32_t beta, posit32_t* C, int64_t ldc) {
+  if (transa != P32_NOTRANS && transa != P32_TRANS) return -2;
+  if (transb != P32_NOTRANS && transb != P32_TRANS) return -3;
+  if (m < 0) return -4;
+  if (n < 0) return -5;
+  if (k < 0) return -6;
+  const int64_t a_width = transa ? m : k;
+  const int64_t b_width = transb ? k : n;
+  if (lda < (a_width > 1 ? a_width : 1)) return -9;
+  if (ldb < (b_width > 1 ? b_width : 1)) return -11;
+  if (ldc < (n > 1 ? n : 1)) return -14;
+  if (m == 0 || n == 0) return 0;
+  if (C == nullptr) return -13;
+  const bool reads_ab = alpha != 0u && k > 0;
+  if (reads_ab && A == nullptr) return -8;
+  if (reads_ab && B == nullptr) return -10;
+  if (reads_ab && ((const void*)C == (const void*)A || (const void*)C == (const void*)B)) return -13;
+  if ((m + 63) / 64 > 65535) return -4;     // grid.y limit of the tiled kernel
+  return p32::launch_gemm((hipStream_t)stream, transa, transb, m, n, k, alpha, A, lda, B, ldb,
+                          beta, C, ldc);
+}
+
+int posit32_from_f64(void* stream, int64_t n, const double* x, posit32_t* out) {
+  if (n < 0) return -2;
+  if (n > 0 && x == nullptr) return -3;
+  if (n > 0 && out == nullptr) return -4;
+  return p32::launch_from_f64((hipStream_t)stream, n, x, out);
+}
+
+int posit32_to_f64(void* stream, int64_t n, const posit32_t* p, double* out) {
+  if (n < 0) return -2;
+  if (n > 0 && p == nullptr) return -3;
+  if (n > 0 && out == nullptr) return -4;
+  return p32::launch_to_f64((hipStream_t)stream, n, p, out);
+}
+
+int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a, const posit32_t* b,
+                        posit32_t* out) {
+  if (op < P32_OP_ADD || op > P32_OP_SQRT) return -2;
+  if (n < 0) return -3;
+  if (n > 0 && a == nullptr) return -4;
+  if (n > 0 && op != P32_OP_SQRT && b == nullptr) return -5;
+  if (n > 0 && out == nullptr) return -6;
+  return p32::launch_elementwise((hipStream_t)stream, op, n, a, b, out);
+}
+
+}  // extern "C"

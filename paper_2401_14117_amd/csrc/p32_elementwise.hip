@@ -1,0 +1,109 @@
+// p32_elementwise.hip -- conversions and elementwise Posit(32,2) arithmetic
+// (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2), on the general exact
+// routines of p32_device.hpp.  Grid-stride loops; every element independent.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "p32_device.hpp"
+#include "p32_launch.hpp"
+
+namespace p32 {
+
+__global__ void from_f64_kernel(int64_t n, const double* __restrict__ x, uint32_t* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    uint32_t r;
+    if (!isfinite(v)) {
+      r = kNaR;
+    } else if (v == 0.0) {
+      r = 0u;
+    } else {
+      const uint64_t bits = (uint64_t)__double_as_longlong(v);
+      const bool neg = bits >> 63;
+      const int bexp = (int)((bits >> 52) & 0x7FF);
+      uint64_t mant = bits & ((((uint64_t)1) << 52) - 1);
+      int x2;
+      if (bexp == 0) {                 // subnormal: mant * 2^-1074
+        x2 = -1074;
+      } else {
+        mant |= ((uint64_t)1) << 52;
+        x2 = bexp - 1075;
+      }
+      r = round_general(neg, mant, x2, false);
+    }
+    out[i] = r;
+  }
+}
+
+__global__ void to_f64_kernel(int64_t n, const uint32_t* __restrict__ p, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = p[i];
+    double r;
+    if (v == kNaR) {
+      r = __longlong_as_double(0x7FF8000000000000LL);
+    } else {
+      const dec d = decode(v);
+      r = d.s == 0 ? 0.0 : ldexp((double)d.s, d.sc - 27);
+    }
+    out[i] = r;
+  }
+}
+
+__global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict__ a,
+                                   const uint32_t* __restrict__ b, uint32_t* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = a[i];
+    const uint32_t y = op == 4 ? 0u : b[i];
+    const bool xn = x == kNaR, yn = y == kNaR;
+    uint32_t r;
+    switch (op) {
+      case 0:
+      case 1: {
+        const uint32_t yy = op == 1 ? 0u - y : y;
+        r = (xn || yn) ? kNaR : add_general(win_of(x), win_of(yy));
+        break;
+      }
+      case 2:
+        r = (xn || yn) ? kNaR : mul_general(decode(x), decode(y));
+        break;
+      case 3:
+        r = div_general(decode(x), decode(y), xn, yn);
+        break;
+      default:
+        r = sqrt_general(decode(x), xn);
+        break;
+    }
+    out[i] = r;
+  }
+}
+
+static dim3 grid_for(int64_t n) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  return dim3((unsigned)blocks);
+}
+
+int launch_from_f64(hipStream_t s, int64_t n, const double* x, uint32_t* out) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(from_f64_kernel, grid_for(n), dim3(256), 0, s, n, x, out);
+  return launch_status();
+}
+
+int launch_to_f64(hipStream_t s, int64_t n, const uint32_t* p, double* out) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(to_f64_kernel, grid_for(n), dim3(256), 0, s, n, p, out);
+  return launch_status();
+}
+
+int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, const uint32_t* b,
+                       uint32_t* out) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(elementwise_kernel, grid_for(n), dim3(256), 0, s, op, n, a, b, out);
+  return launch_status();
+}
+
+}  // namespace p32

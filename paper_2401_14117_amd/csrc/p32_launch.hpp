@@ -1,0 +1,23 @@
+// p32_launch.hpp -- launch helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p32 {
+
+// Status of the most recent launch as a library return code.
+inline int launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : -1000 - (int)e;
+}
+
+int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+                const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
+                uint32_t* C, int64_t ldc);
+int launch_from_f64(hipStream_t s, int64_t n, const double* x, uint32_t* out);
+int launch_to_f64(hipStream_t s, int64_t n, const uint32_t* p, double* out);
+int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, const uint32_t* b,
+                       uint32_t* out);
+
+}  // namespace p32

@@ -1,0 +1,143 @@
+"""ctypes binding of libposit32.so (C ABI in include/posit32.h).
+
+Argument marshalling only: every operation runs in the HIP library on the
+caller's current torch stream.  Posit(32,2) values are carried in
+``torch.int32`` device tensors holding the raw bit patterns (a signed view of
+the uint32 pattern).  Scalars (alpha, beta) are Python ints holding patterns.
+If the library has not been built, or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libposit32.so")
+
+NAR = 0x80000000
+ONE = 0x40000000
+ZERO = 0
+MINUS_ONE = 0xC0000000
+
+OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_SQRT = range(5)
+
+_lib = None
+
+
+class Posit32Error(RuntimeError):
+    pass
+
+
+def lib() -> ctypes.CDLL:
+    """Load libposit32.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise Posit32Error(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
+    L.posit32_version.restype = i32
+    L.posit32_strerror.argtypes = [i32]
+    L.posit32_strerror.restype = ctypes.c_char_p
+    L.posit32_gemm.argtypes = [vp, i32, i32, i64, i64, i64, u32, vp, i64, vp, i64, u32, vp, i64]
+    L.posit32_gemm.restype = i32
+    L.posit32_from_f64.argtypes = [vp, i64, vp, vp]
+    L.posit32_to_f64.argtypes = [vp, i64, vp, vp]
+    L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
+    for f in (L.posit32_from_f64, L.posit32_to_f64, L.posit32_elementwise):
+        f.restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = lib().posit32_strerror(rc).decode()
+        raise Posit32Error(f"{what} failed with code {rc}: {msg}")
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.numel() and t.stride(1) != 1:
+        raise ValueError("matrices must have unit column stride (row-major)")
+    return max(t.stride(0), 1) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def _is_i32_cuda(t: torch.Tensor) -> None:
+    if t.dtype != torch.int32 or not t.is_cuda:
+        raise TypeError("posit tensors must be torch.int32 on a CUDA (HIP) device")
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, alpha: int = ONE, beta: int = ONE,
+         transa: bool = False, transb: bool = False, stream=None) -> torch.Tensor:
+    """In place: C = alpha*op(A)*op(B) + beta*C (Posit(32,2)); returns C."""
+    for t in (A, B, C):
+        _is_i32_cuda(t)
+    m, n = C.shape
+    k = A.shape[0] if transa else A.shape[1]
+    if (A.shape[1] if transa else A.shape[0]) != m:
+        raise ValueError("op(A) rows must equal C rows")
+    if (B.shape[1] if transb else B.shape[0]) != k or (B.shape[0] if transb else B.shape[1]) != n:
+        raise ValueError("op(B) must be k x n")
+    rc = lib().posit32_gemm(_stream(stream), int(transa), int(transb), m, n, k,
+                            alpha & 0xFFFFFFFF, _ptr(A), _ld(A), _ptr(B), _ld(B),
+                            beta & 0xFFFFFFFF, _ptr(C), _ld(C))
+    _check(rc, "posit32_gemm")
+    return C
+
+
+def gemm_raw(transa: int, transb: int, m: int, n: int, k: int, alpha: int, A_ptr, lda: int,
+             B_ptr, ldb: int, beta: int, C_ptr, ldc: int, stream=None) -> int:
+    """Direct call of the C entry point with raw pointers; returns its code."""
+    return lib().posit32_gemm(_stream(stream) if torch.cuda.is_available() else None,
+                              transa, transb, m, n, k, alpha & 0xFFFFFFFF, A_ptr, lda,
+                              B_ptr, ldb, beta & 0xFFFFFFFF, C_ptr, ldc)
+
+
+def from_f64(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("from_f64 expects a float64 CUDA tensor")
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    _check(lib().posit32_from_f64(_stream(stream), x.numel(), _ptr(x), _ptr(out)), "posit32_from_f64")
+    return out
+
+
+def to_f64(p: torch.Tensor, stream=None) -> torch.Tensor:
+    _is_i32_cuda(p)
+    p = p.contiguous()
+    out = torch.empty(p.shape, dtype=torch.float64, device=p.device)
+    _check(lib().posit32_to_f64(_stream(stream), p.numel(), _ptr(p), _ptr(out)), "posit32_to_f64")
+    return out
+
+
+def elementwise(op: int, a: torch.Tensor, b: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _is_i32_cuda(a)
+    a = a.contiguous()
+    if b is not None:
+        _is_i32_cuda(b)
+        b = b.contiguous()
+        if b.shape != a.shape:
+            raise ValueError("shape mismatch")
+    out = torch.empty_like(a)
+    _check(lib().posit32_elementwise(_stream(stream), op, a.numel(), _ptr(a), _ptr(b), _ptr(out)),
+           "posit32_elementwise")
+    return out
+
+
+def version() -> int:
+    return lib().posit32_version()

@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects invalid arguments before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "posit32.h")).read()
+    return sorted(set(re.findall(r"\b(posit32_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2401_14117_amd import posit32
+    return posit32.lib()
+
+
+def test_header_symbols_exported(L):
+    syms = _declared_symbols()
+    assert "posit32_gemm" in syms and len(syms) >= 5
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_version_and_strerror(L):
+    assert L.posit32_version() >= 100
+    assert L.posit32_strerror(0) == b"ok"
+    assert b"argument" in L.posit32_strerror(-3)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((2, 0, 4, 4, 4, 8, 4, 8, 4, 8, 4), -2),      # bad transa
+    ((0, 7, 4, 4, 4, 8, 4, 8, 4, 8, 4), -3),      # bad transb
+    ((0, 0, -1, 4, 4, 8, 4, 8, 4, 8, 4), -4),     # m < 0
+    ((0, 0, 4, -1, 4, 8, 4, 8, 4, 8, 4), -5),     # n < 0
+    ((0, 0, 4, 4, -1, 8, 4, 8, 4, 8, 4), -6),     # k < 0
+    ((0, 0, 4, 4, 4, 8, 3, 8, 4, 8, 4), -9),      # lda < k
+    ((1, 0, 5, 4, 4, 8, 4, 8, 4, 8, 5), -9),      # lda < m for A^T
+    ((0, 0, 4, 4, 4, 8, 4, 8, 3, 8, 4), -11),     # ldb < n
+    ((0, 1, 4, 4, 5, 8, 5, 8, 4, 8, 4), -11),     # ldb < k for B^T
+    ((0, 0, 4, 4, 4, 8, 4, 8, 4, 8, 3), -14),     # ldc < n
+    ((0, 0, 4, 4, 4, 0, 4, 8, 4, 8, 4), -8),      # A null
+    ((0, 0, 4, 4, 4, 8, 4, 0, 4, 8, 4), -10),     # B null
+    ((0, 0, 4, 4, 4, 8, 4, 8, 4, 0, 4), -13),     # C null
+    ((0, 0, 4, 4, 4, 8, 4, 16, 4, 8, 4), -13),    # C aliases A (A = C = 8)
+])
+def test_gemm_argument_errors(L, args, code):
+    ta, tb, m, n, k, A, lda, B, ldb, C, ldc = args
+    # pointers are never dereferenced: validation fails before any launch
+    rc = L.posit32_gemm(None, ta, tb, m, n, k, 0x40000000, A or None, lda, B or None, ldb,
+                        0x40000000, C or None, ldc)
+    assert rc == code
+
+
+def test_gemm_noop_shapes_return_ok(L):
+    # m == 0 or n == 0: nothing to do, null pointers allowed
+    assert L.posit32_gemm(None, 0, 0, 0, 5, 5, 0x40000000, None, 5, None, 5, 0, None, 5) == 0
+    assert L.posit32_gemm(None, 0, 0, 5, 0, 5, 0x40000000, None, 5, None, 1, 0, None, 1) == 0
+
+
+def test_other_argument_errors(L):
+    assert L.posit32_from_f64(None, -1, None, None) == -2
+    assert L.posit32_from_f64(None, 4, None, 8) == -3
+    assert L.posit32_to_f64(None, 4, 8, None) == -4
+    assert L.posit32_elementwise(None, 9, 4, 8, 8, 8) == -2
+    assert L.posit32_elementwise(None, 0, -4, 8, 8, 8) == -3
+    assert L.posit32_elementwise(None, 0, 4, 8, None, 8) == -5
+    assert L.posit32_from_f64(None, 0, None, None) == 0

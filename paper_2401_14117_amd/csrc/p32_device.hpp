@@ -20,8 +20,8 @@
 //    staged, not once per operation (the paper's pre-processing, Section 2).
 //
 //  * Window form (products and running sums): a signed 32-bit h with
-//    |h| <= 2^29 and an exponent e, x = h * 2^(e - 28).  Rounded values keep
-//    their significand bits at h[28..1]; e is the scale (one less for the
+//    |h| <= 2^28 and an exponent e, x = h * 2^(e - 27).  Rounded values keep
+//    their significand bits at h[27..0]; e is the scale (one less for the
 //    exact value -2^e' whose two's complement normalises one bit lower, which
 //    never changes a result because such a value is exact).  Zero is h = 0,
 //    e = EZERO.  Values stay decoded across the whole k loop; the bit pattern
@@ -51,7 +51,7 @@ struct dec {
 };
 
 struct win {
-  int32_t h;    // |h| <= 2^29
+  int32_t h;    // |h| <= 2^28
   int32_t e;
 };
 
@@ -84,7 +84,7 @@ __device__ __forceinline__ dec decode(uint32_t p) {
 
 __device__ __forceinline__ win to_win(dec d) {
   win w;
-  w.h = d.s * 2;
+  w.h = d.s;
   w.e = d.s ? d.sc : kEZero;
   return w;
 }
@@ -147,7 +147,7 @@ __device__ inline uint32_t encode_exact(win a) {
   if (a.h == 0) return 0u;
   const bool neg = a.h < 0;
   const uint64_t m = (uint64_t)(neg ? -(int64_t)a.h : a.h);
-  return round_general(neg, m, a.e - 28, false);
+  return round_general(neg, m, a.e - 27, false);
 }
 
 // exact sum of two window-form values (each exactly a posit), rounded
@@ -167,13 +167,13 @@ __device__ inline uint32_t add_general(win a, win b) {
   if (d <= 96) {                                  // exact alignment
     M1 = (unsigned __int128)m1 << d;
     M2 = m2;
-    x = q.e - 28;
+    x = q.e - 27;
   } else {                                        // operand 2 lies far below
     M1 = (unsigned __int128)m1 << 96;             // the rounding point: keep
     const int sh = d - 96;                        // its floor and a sticky flag
     M2 = sh >= 64 ? 0 : (m2 >> sh);
     lost = sh >= 64 ? m2 != 0 : (m2 & ((((uint64_t)1) << sh) - 1)) != 0;
-    x = p.e - 28 - 96;
+    x = p.e - 27 - 96;
   }
   if (n1 == n2) return round_general(n1, M1 + M2, x, lost);
   if (M1 == M2 && !lost) return 0u;               // exact cancellation: +0
@@ -228,50 +228,82 @@ __device__ __forceinline__ int ffbh_i32(int32_t x) {
   return r;
 }
 
-// Round a 64-bit two's-complement value whose leading significant bit is at
-// bit 61 to the posit precision of scale sc (fraction length f_s = 27 - (m-1)
-// for regime length m, valid for f_s >= 1), returning window form.  The low
-// word only matters as a sticky bit, which is folded into bit 0 of the high
-// word (the rounding point is at bit >= 2 of the high word, so this is a
-// round-to-odd pre-rounding that leaves round-to-nearest-even unchanged).
-__device__ __forceinline__ win round_win(uint64_t v, int sc) {
-  int32_t h = (int32_t)(v >> 32);
-  h |= (uint32_t)v != 0u ? 1 : 0;
-  const int t = sc ^ (sc >> 31);                 // |sc| or |sc|-1: regime index
-  const int r = 2 + (t >> 2);                    // 29 - f_s
-  const int lsb = (h >> (r & 31)) & 1;          // (r is only garbage on lanes
-  const int32_t half_m1 = (1 << ((r - 1) & 31)) - 1;   // the caller flags)
-  int32_t hr = h + half_m1 + lsb;
-  hr &= ~((1 << (r & 31)) - 1);
+__device__ __forceinline__ uint32_t bfm(int width) {   // (1 << width) - 1
+  uint32_t r;
+  asm("v_bfm_b32 %0, %1, 0" : "=v"(r) : "v"(width));
+  return r;
+}
+
+// Fold the low word of a 64-bit value into the high word as a sticky bit:
+// returns 2*hi + (lo != 0), a round-to-odd pre-rounding one bit below hi.
+__device__ __forceinline__ int32_t fold_sticky(uint64_t v) {
+  const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+  uint32_t r;
+  uint64_t carry;   // lane mask (lo != 0), fed back as the carry-in
+  asm("v_cmp_ne_u32_e64 %1, 0, %2\n\tv_addc_co_u32_e64 %0, %1, %3, %3, %1"
+      : "=v"(r), "=&s"(carry) : "v"(lo), "v"(hi));
+  return (int32_t)r;
+}
+
+// Round h2 (leading significant bit at bit 29, sticky in bit 0) to the posit
+// precision of scale sc: f_s = 27 - s fraction bits with s = m - 1 the regime
+// index, valid for f_s >= 1.  The kept bits are h2[29 .. s+2]; the guard bit
+// is h2[s+1], so bit 0 is always below it and the round-to-odd sticky leaves
+// round-to-nearest-even unchanged.  Returns window form (leading bit at 27).
+__device__ __forceinline__ win round_h2(int32_t h2, int sc) {
+  const int t = sc ^ (sc >> 31);                 // sc >= 0 ? sc : -sc - 1
+  const int s = t >> 2;                          // regime index m - 1
+  const int r = s + 2;                           // rounding position
+  const int32_t half_m1 = (int32_t)bfm(s + 1);   // 2^(r-1) - 1
+  const int32_t lsb = (int32_t)__builtin_amdgcn_ubfe((uint32_t)h2, (uint32_t)r, 1u);
+  const int32_t q = (h2 + half_m1 + lsb) >> r;   // nearest, ties to even
   win w;
-  w.h = hr >> 1;
+  w.h = q << s;
   w.e = sc;
   return w;
 }
 
-// product of decoded operands given as a8 = s_a << 3 and b4 = s_b << 2
-__device__ __forceinline__ bool mul_fast(int32_t a8, int32_t sca, int32_t b4, int32_t scb, win& out) {
-  const int64_t P = (int64_t)a8 * (int64_t)b4;   // |P| in [2^59, 2^61)
+// product of decoded operands given as a8 = s_a << 3 and b4 = s_b << 2:
+// |P| in [2^59, 2^61), normalised to a leading bit at 60.
+__device__ __forceinline__ win mul_core(int32_t a8, int32_t sca, int32_t b4, int32_t scb, int& c3) {
+  const int64_t P = (int64_t)a8 * (int64_t)b4;
   const int cnt = ffbh_i32((int32_t)(P >> 32));
-  const int c2 = cnt - 2;
+  c3 = cnt - 3;
   const int sc = sca + scb + 4 - cnt;
-  const bool ok = ((unsigned)c2 < 30u) & ((unsigned)(sc + 108) < 216u);
-  out = round_win((uint64_t)P << (c2 & 63), sc);
-  return ok;
+  return round_h2(fold_sticky((uint64_t)P << (c3 & 63)), sc);
 }
 
-__device__ __forceinline__ bool add_fast(win a, win b, win& out) {
+// sum of two window-form values: both are aligned to the larger exponent
+// (bit 59 <-> 2^E) in 64-bit two's complement, so |S| <= 2^61.  An operand
+// shifted past bit 0 only loses bits far below the rounding point (it then
+// sits >= 33 bits below the other one, whose last bit is at >= 32), where the
+// truncation toward -inf cannot cross a rounding boundary.
+__device__ __forceinline__ win add_core(win a, win b, int& c3) {
   const int E = a.e > b.e ? a.e : b.e;
   const int da = min(E - a.e, 63), db = min(E - b.e, 63);
   const int64_t X = ((int64_t)a.h << 32) >> da;
   const int64_t Y = ((int64_t)b.h << 32) >> db;
-  const int64_t S = X + Y;                        // |S| <= 2^62
+  const int64_t S = X + Y;
   const int cnt = ffbh_i32((int32_t)(S >> 32));
-  const int c2 = cnt - 2;
-  const int sc = E + 3 - cnt;
-  const bool ok = ((unsigned)c2 < 30u) & ((unsigned)(sc + 108) < 216u);
-  out = round_win((uint64_t)S << (c2 & 63), sc);
-  return ok;
+  c3 = cnt - 3;                                  // valid when 0 <= c3 < 29
+  const int sc = E + 4 - cnt;
+  return round_h2(fold_sticky((uint64_t)S << (c3 & 63)), sc);
+}
+
+// fast-range test of a result scale: f_s >= 1 and outside the tapered regime
+__device__ __forceinline__ bool scale_ok(int sc) { return (unsigned)(sc + 108) < 216u; }
+
+// checked forms: return false when the lane must take the exact rare path
+__device__ __forceinline__ bool mul_fast(int32_t a8, int32_t sca, int32_t b4, int32_t scb, win& out) {
+  int c3;
+  out = mul_core(a8, sca, b4, scb, c3);
+  return ((unsigned)c3 < 3u) & scale_ok(out.e);
+}
+
+__device__ __forceinline__ bool add_fast(win a, win b, win& out) {
+  int c3;
+  out = add_core(a, b, c3);
+  return ((unsigned)c3 < 29u) & scale_ok(out.e);
 }
 
 // general product of two decoded operands, in window form

@@ -44,6 +44,47 @@ __device__ __noinline__ uint32_t gemm_epilogue(win acc, int nar, uint32_t alpha,
   return r;
 }
 
+// One k step for the thread's TM x TN accumulators.  CHECKED also tests the
+// product and sum scales and zero products; the unchecked form only tests
+// the sum for cancellation (its callers guarantee the rest).  Flagged lanes
+// redo the whole step on the exact path.
+template <bool CHECKED>
+__device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restrict__ Arow,
+                                       const int2* __restrict__ Brow, int tx, int ty) {
+  int2 a[TM], b[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) a[i] = Arow[ty * TM + i];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) b[j] = Brow[tx * TN + j];
+  win nacc[TM][TN];
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      if (CHECKED) {
+        win pr;
+        bad |= !mul_fast(a[i].x, a[i].y, b[j].x, b[j].y, pr);
+        bad |= !add_fast(acc[i][j], pr, nacc[i][j]);
+      } else {
+        int c3p, c3;
+        const win pr = mul_core(a[i].x, a[i].y, b[j].x, b[j].y, c3p);
+        nacc[i][j] = add_core(acc[i][j], pr, c3);
+        bad |= (unsigned)c3 >= 29u;
+      }
+    }
+  if (bad) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) nacc[i][j] = madd_slow(acc[i][j], a[i].x, a[i].y, b[j].x, b[j].y);
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = nacc[i][j];
+}
+
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(NT)
 gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
@@ -65,6 +106,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
     for (int j = 0; j < TN; ++j) { acc[i][j].h = 0; acc[i][j].e = kEZero; }
 
   for (int64_t p0 = 0; p0 < k; p0 += BK) {
+    int my_ok = 1;
     __syncthreads();
 #pragma unroll
     for (int l = 0; l < (BM * BK) / NT; ++l) {
@@ -78,6 +120,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
       else v = TA ? A[gp * lda + gi] : A[gi * lda + gp];
       if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
       const dec d = decode(v);
+      my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
       As[pp][ii] = make_int2(d.s * 8, d.sc);
     }
 #pragma unroll
@@ -92,38 +135,31 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
       else v = TB ? B[gj * ldb + gp] : B[gp * ldb + gj];
       if (v == kNaR) { colNaR[jj] = 1; v = kOne; }
       const dec d = decode(v);
+      my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
       Bs[pp][jj] = make_int2(d.s * 4, d.sc);
     }
-    __syncthreads();
+    // Block-uniform choice of the inner loop for this k-tile.  The unchecked
+    // loop is exact when every staged operand is nonzero with scale in
+    // [-53, 49] (products then have scales in [-106, 99]) and every
+    // accumulator is zero or has scale in [-106, 100].  Sums then keep
+    // scales in [-108, 104], inside the fast range: with |p| >= 2^-106, a
+    // sum acc + p either has |acc| < |p|/2 and so |sum| > 2^-107, or both
+    // terms are multiples of 2^-108 and a nonzero sum is >= 2^-108; and 16
+    // products below 2^100 cannot lift |acc| < 2^101 past 2^105.  Only
+    // cancellation to zero or by more than 28 bits is left to test.
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        my_ok &= (acc[i][j].h == 0) | ((unsigned)(acc[i][j].e + 106) <= 206u);
+    const bool safe = __syncthreads_and(my_ok);
 
+    if (safe) {
 #pragma unroll 1
-    for (int p = 0; p < BK; ++p) {
-      int2 a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[p][ty * TM + i];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[p][tx * TN + j];
-      win nacc[TM][TN];
-      bool bad = false;
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          win pr, s;
-          bad |= !mul_fast(a[i].x, a[i].y, b[j].x, b[j].y, pr);
-          bad |= !add_fast(acc[i][j], pr, s);
-          nacc[i][j] = s;
-        }
-      if (bad) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) nacc[i][j] = madd_slow(acc[i][j], a[i].x, a[i].y, b[j].x, b[j].y);
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = nacc[i][j];
+      for (int p = 0; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], tx, ty);
+    } else {
+#pragma unroll 1
+      for (int p = 0; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], tx, ty);
     }
   }
   __syncthreads();

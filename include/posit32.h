@@ -75,7 +75,8 @@ const char* posit32_strerror(int code);
  *   m == 0 or n == 0: nothing is done.
  * Errors: -2/-3 bad trans flag, -4/-5/-6 negative m/n/k, -8/-9 null A or bad
  * lda, -10/-11 null B or bad ldb, -13/-14 null C or bad ldc, -13 also when C
- * aliases A or B (same base pointer).
+ * aliases A or B (same base pointer); -4 also when m*n needs more than 2^24
+ * output tiles of 64 x 32 (one launch).
  */
 int posit32_gemm(void* stream, int transa, int transb, int64_t m, int64_t n,
                  int64_t k, posit32_t alpha, const posit32_t* A, int64_t lda,

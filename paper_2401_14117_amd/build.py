@@ -28,14 +28,18 @@ def flags() -> list[str]:
             "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str | None = None, defines: list[str] | None = None) -> str:
+    """Compile and link the library (to `out`, default in-tree); `defines`
+    are extra -D options for tuning builds."""
     cc = hipcc()
-    objdir = os.path.join(HERE, "_build")
+    lib = out or LIB
+    extra = ["-D" + d for d in (defines or [])]
+    objdir = os.path.join(os.path.dirname(lib), "_build_" + os.path.basename(lib).replace(".", "_"))
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [cc] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc] + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [cc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I",
                    os.path.join(HERE, "..", "include"), "-c", os.path.join(CSRC, src), "-o", obj]
@@ -49,16 +53,17 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     r = subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs,
                        capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libposit32.so failed")
-    os.replace(tmp, LIB)
-    from paper_2401_14117_amd import isa_count
-    isa_count.write_report(cc, flags(), os.path.join(HERE, "libposit32.isa.json"))
-    return LIB
+    os.replace(tmp, lib)
+    if out is None:
+        from paper_2401_14117_amd import isa_count
+        isa_count.write_report(cc, flags(), os.path.join(HERE, "libposit32.isa.json"))
+    return lib
 
 
 if __name__ == "__main__":

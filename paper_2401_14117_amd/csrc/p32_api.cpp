@@ -36,7 +36,6 @@ int posit32_gemm(void* stream, int transa, int transb, int64_t m, int64_t n, int
   if (reads_ab && A == nullptr) return -8;
   if (reads_ab && B == nullptr) return -10;
   if (reads_ab && ((const void*)C == (const void*)A || (const void*)C == (const void*)B)) return -13;
-  if ((m + 63) / 64 > 65535) return -4;     // grid.y limit of the tiled kernel
   return p32::launch_gemm((hipStream_t)stream, transa, transb, m, n, k, alpha, A, lda, B, ldb,
                           beta, C, ldc);
 }

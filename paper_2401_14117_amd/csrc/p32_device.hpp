@@ -263,6 +263,28 @@ __device__ __forceinline__ win round_h2(int32_t h2, int sc) {
   return w;
 }
 
+// Rounding parameters of one scale, packed for round_lut:
+//   x = (2^(r-1) - 1) << 5 | r   (r = s + 2 in the low five bits, where the
+//                                  shift and bit-field instructions read it)
+//   y = ~(2^r - 1)               (clears the bits below the rounding point)
+__device__ __forceinline__ uint2 round_params(int sc) {
+  const int t = sc ^ (sc >> 31);
+  int s = t >> 2;
+  if (s > 26) s = 26;                            // f_s = 0 or tapered: unused
+  const int r = s + 2;
+  uint2 p;
+  p.x = (((1u << (r - 1)) - 1u) << 5) | (uint32_t)r;
+  p.y = ~((1u << r) - 1u);
+  return p;
+}
+
+// round_h2 with the scale-dependent parameters taken from a table entry
+__device__ __forceinline__ int32_t round_lut(int32_t h2, uint2 p) {
+  const int32_t lsb = (int32_t)__builtin_amdgcn_ubfe((uint32_t)h2, p.x, 1u);
+  const int32_t q = h2 + (int32_t)(p.x >> 5) + lsb;
+  return (q & (int32_t)p.y) >> 2;
+}
+
 // product of decoded operands given as a8 = s_a << 3 and b4 = s_b << 2:
 // |P| in [2^59, 2^61), normalised to a leading bit at 60.
 __device__ __forceinline__ win mul_core(int32_t a8, int32_t sca, int32_t b4, int32_t scb, int& c3) {

@@ -17,7 +17,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL = "_ZN3p3211gemm_kernelILb0ELb0EEEvlllPKjlS2_lPjljj"
-MADDS_PER_STEP = 16   # TM * TN of the kernel
+MADDS_PER_STEP = 8    # TM * TN of the kernel
 
 
 def source_hash() -> str:

@@ -14,7 +14,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libposit32.so")
+# POSIT32_LIB may name another build of the same library (same C ABI)
+LIB_PATH = os.environ.get("POSIT32_LIB") or os.path.join(HERE, "libposit32.so")
 
 NAR = 0x80000000
 ONE = 0x40000000

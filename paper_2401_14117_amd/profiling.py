@@ -1,0 +1,142 @@
+"""Summaries of rocprofv3 output for the Rgemm kernel (a reporting utility).
+
+rocprofv3 is run on the MI355X machine by the commands recorded in each summary;
+this module only reads the CSV files it writes:
+
+* ``<dir>/*_kernel_trace.csv`` (``--kernel-trace --output-format csv``):
+  per-dispatch start/end timestamps, from which per-kernel call counts and
+  average durations are taken;
+* ``<dir>/*_counter_collection.csv`` (``--pmc ...``): per-dispatch counter
+  values.  FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.
+
+HBM traffic of a kernel is FETCH_SIZE + WRITE_SIZE, each scaled by the ratio
+between the known size of a plain device copy and what the same counter reads
+for that copy (run under the same profiler in the same job).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import json
+import os
+
+
+def _one(d: str, suffix: str) -> str:
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return sorted(files)[0]
+
+
+def kernel_stats(trace_dir: str) -> dict:
+    """name -> (calls, average duration in ns) from a kernel trace."""
+    acc = collections.defaultdict(list)
+    with open(_one(trace_dir, "_kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            acc[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def counter_per_dispatch(pmc_dir: str, counter: str, match: str) -> float:
+    """Average per-dispatch value of a counter over dispatches of kernels
+    whose name contains `match`."""
+    per = collections.defaultdict(float)
+    with open(_one(pmc_dir, "_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and match in r["Kernel_Name"]:
+                per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+    if not per:
+        raise ValueError(f"no {counter} samples for kernels matching {match!r}")
+    return sum(per.values()) / len(per)
+
+
+def summarize(args) -> None:
+    stats = kernel_stats(args.trace)
+    copy_bytes = args.copy_bytes
+    fetch_f = copy_bytes / (1024.0 * counter_per_dispatch(args.copy_fetch, "FETCH_SIZE", args.copy_kernel))
+    write_f = copy_bytes / (1024.0 * counter_per_dispatch(args.copy_write, "WRITE_SIZE", args.copy_kernel))
+    fetch_kib = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
+    write_kib = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    hbm = fetch_kib * 1024 * fetch_f + write_kib * 1024 * write_f
+    name = next(k for k in stats if args.kernel in k)
+    calls, avg_ns = stats[name]
+    m, n, k = args.mnk
+    algo = 4 * (m * k + k * n + 2 * m * n)
+    lines = [
+        f"# rocprofv3: Posit(32,2) Rgemm kernel, {args.workload}",
+        "",
+        f"Kernel: `{name}`",
+        f"Workload: {args.workload} (m = {m}, n = {n}, k = {k}).",
+        f"Kernel source hash: {args.kernel_hash}.",
+        "",
+        "Commands (run on the MI355X box from /tmp, REPO = the repository root):",
+        "",
+        "```",
+        f"rocprofv3 --kernel-trace --output-format csv -d $REPO/gpurun_out/trace -o trace -- "
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 2 --warmup 1 --cpu-budget 0",
+        f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/fetch -o fetch -- "
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
+        f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/write -o write -- "
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
+        "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/copyf -o copyf -- "
+        "python3 $REPO/bench.py --copy-calibration",
+        "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/copyw -o copyw -- "
+        "python3 $REPO/bench.py --copy-calibration",
+        "```",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| kernel calls (trace run) | {calls} |",
+        f"| average kernel duration | {avg_ns / 1e6:.3f} ms |",
+        f"| Gpops/s from the trace (2mnk / duration) | {2.0 * m * n * k / avg_ns:.1f} |",
+        f"| FETCH_SIZE per dispatch | {fetch_kib:.0f} KiB |",
+        f"| WRITE_SIZE per dispatch | {write_kib:.0f} KiB |",
+        f"| copy calibration ({copy_bytes >> 20} MiB copy): fetch factor | {fetch_f:.3f} |",
+        f"| copy calibration: write factor | {write_f:.3f} |",
+        f"| HBM traffic per dispatch (scaled) | {hbm / 1e9:.3f} GB |",
+        f"| algorithmic bytes 4(mk + kn + 2mn) | {algo / 1e9:.3f} GB |",
+        f"| HBM bandwidth used | {hbm / (avg_ns * 1e-9) / 1e9:.1f} GB/s (of 8000) |",
+    ]
+    others = sorted(((v[1] * v[0], k, v) for k, v in stats.items() if k != name), reverse=True)[:4]
+    if others:
+        lines += ["", "Other kernels in the traced run (setup: conversions, masks, copies):", ""]
+        for _, kname, (c, a) in others:
+            short = kname if len(kname) < 80 else kname[:77] + "..."
+            lines.append(f"- `{short}`: {c} calls, {a / 1e3:.1f} us average")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if args.traffic_json:
+        data = {}
+        if os.path.exists(args.traffic_json):
+            with open(args.traffic_json) as f:
+                data = json.load(f)
+        data[args.workload] = {"kernel_hash": args.kernel_hash, "hbm_bytes_per_launch": round(hbm),
+                               "fetch_kib": fetch_kib, "write_kib": write_kib,
+                               "fetch_factor": fetch_f, "write_factor": write_f,
+                               "avg_kernel_ms": avg_ns / 1e6}
+        with open(args.traffic_json, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--copy-kernel", default="copyBuffer")
+    ap.add_argument("--kernel", default="gemm_kernel<false, false>")
+    ap.add_argument("--workload", default="square_n8192")
+    ap.add_argument("--mnk", type=int, nargs=3, default=[8192, 8192, 8192])
+    ap.add_argument("--kernel-hash", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic-json")
+    summarize(ap.parse_args())
+
+
+if __name__ == "__main__":
+    main()

@@ -201,3 +201,48 @@ def gemm_entries(A, B, rows, cols, Cin, alpha: int = ONE32, beta: int = ONE32,
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+# ---- factorisations and solves --------------------------------------------------
+
+def getrf(A, nb: int = 256):
+    """Blocked LU with partial pivoting (order in ref_lapack.c).
+    Returns (LU, ipiv (0-based int32), info)."""
+    A = np.array(A, dtype=np.uint32, copy=True, order="C")
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    ipiv = np.zeros(n, dtype=np.int32)
+    info = np.zeros(1, dtype=np.int32)
+    lib().oracle_getrf(n, nb, _ptr(A), n, _ptr(ipiv), _ptr(info))
+    return A, ipiv, int(info[0])
+
+
+def getrs(LU, ipiv, B):
+    LU = np.ascontiguousarray(LU, dtype=np.uint32)
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    X = np.array(B, dtype=np.uint32, copy=True, order="C")
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    n = LU.shape[0]
+    lib().oracle_getrs(n, X.shape[1], _ptr(LU), n, _ptr(ipiv), _ptr(X), X.shape[1])
+    return X
+
+
+def potrf(A, nb: int = 256):
+    """Blocked lower Cholesky (order in ref_lapack.c).  Returns (L, info);
+    only the lower triangle of L is meaningful, the rest is A's."""
+    A = np.array(A, dtype=np.uint32, copy=True, order="C")
+    n = A.shape[0]
+    info = np.zeros(1, dtype=np.int32)
+    lib().oracle_potrf(n, nb, _ptr(A), n, _ptr(info))
+    return A, int(info[0])
+
+
+def potrs(L, B):
+    L = np.ascontiguousarray(L, dtype=np.uint32)
+    X = np.array(B, dtype=np.uint32, copy=True, order="C")
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    n = L.shape[0]
+    lib().oracle_potrs(n, X.shape[1], _ptr(L), n, _ptr(X), X.shape[1])
+    return X

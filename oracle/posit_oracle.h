@@ -63,6 +63,21 @@ void oracle_gemm_entries(int transa, int transb, int64_t k, uint32_t alpha,
                          const int64_t* rows, const int64_t* cols,
                          const uint32_t* Cin, uint32_t* out);
 
+/* ---- factorisations and solves (Posit(32,2), row-major) ----------------
+ * Right-looking blocked algorithms with block size nb; ref_lapack.c states
+ * the order of every operation.  ipiv is 0-based: row c was interchanged
+ * with row ipiv[c].  info: 0 ok; >0 = 1-based column of the first zero pivot
+ * (getrf, which completes) or of the first non-positive/NaR diagonal
+ * (potrf, which stops there).  potrf/potrs use the lower triangle only.  */
+void oracle_getrf(int64_t n, int64_t nb, uint32_t* A, int64_t lda,
+                  int32_t* ipiv, int32_t* info);
+void oracle_getrs(int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+                  const int32_t* ipiv, uint32_t* B, int64_t ldb);
+void oracle_potrf(int64_t n, int64_t nb, uint32_t* A, int64_t lda,
+                  int32_t* info);
+void oracle_potrs(int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda,
+                  uint32_t* B, int64_t ldb);
+
 /* number of OpenMP threads the oracle's parallel loops use */
 int oracle_num_threads(void);
 

@@ -102,3 +102,30 @@ def apply_masks(patterns: np.ndarray, mat: Matrix) -> np.ndarray:
     if mat.nar_mask is not None:
         patterns[mat.nar_mask] = 0x80000000
     return patterns
+
+
+@dataclass
+class SolveCase:
+    name: str
+    n: int
+    A: np.ndarray          # float64 n x n
+    b: np.ndarray          # float64 n x nrhs
+    kind: str              # "lu" or "chol"
+
+
+def lu_case(n: int, nrhs: int = 1) -> SolveCase:
+    """LU factor+solve input: A ~ uniform[-1,1] (seed 4000+n), b = A * ones."""
+    rng = np.random.default_rng(4000 + n)
+    A = rng.uniform(-1.0, 1.0, (n, n))
+    b = A @ np.ones((n, nrhs))
+    return SolveCase(f"getrf_n{n}", n, A, b, "lu")
+
+
+def chol_case(n: int, nrhs: int = 1) -> SolveCase:
+    """Cholesky factor+solve input: A = B B^T / n + I with B ~ uniform[-1,1]
+    (seed 5000+n), b = A * ones."""
+    rng = np.random.default_rng(5000 + n)
+    Bm = rng.uniform(-1.0, 1.0, (n, n))
+    A = Bm @ Bm.T / n + np.eye(n)
+    b = A @ np.ones((n, nrhs))
+    return SolveCase(f"potrf_n{n}", n, A, b, "chol")

@@ -79,6 +79,75 @@ def make_case(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_solve_bench(name: str, args, dev) -> dict:
+    """Factor + solve workloads (getrf_nN / potrf_nN): one step = copy the
+    matrix into the work buffer, factor it, solve A x = b (nrhs = 1)."""
+    import torch
+    from paper_2401_14117_amd import posit32
+    from paper_2401_14117_amd import workloads as W
+    kind, n = name.split("_n")
+    n = int(n)
+    case = W.lu_case(n) if kind == "getrf" else W.chol_case(n)
+    A0 = posit32.from_f64(torch.from_numpy(case.A).to(dev))
+    b0 = posit32.from_f64(torch.from_numpy(np.ascontiguousarray(case.b)).to(dev))
+    A = torch.empty_like(A0)
+    b = torch.empty_like(b0)
+    stream = torch.cuda.current_stream()
+
+    def step(ev0=None, ev1=None):
+        A.copy_(A0)
+        b.copy_(b0)
+        if ev0 is not None:
+            ev0.record(stream)
+        if kind == "getrf":
+            _, ipiv, info = posit32.getrf(A, args.nb)
+            posit32.getrs(A, ipiv, b)
+        else:
+            _, info = posit32.potrf(A, args.nb)
+            posit32.potrs(A, b)
+        if ev1 is not None:
+            ev1.record(stream)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        info = step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    pops = (2.0 if kind == "getrf" else 1.0) * n ** 3 / 3.0
+    ms_per_step = wall * 1e3 / args.steps
+    # accuracy of the solve (outside the timed region): forward error against
+    # an FP64 solve, beside LAPACK binary32 (sgetrs/spotrs) on the same data
+    import scipy.linalg as sl
+    x = posit32.to_f64(b).cpu().numpy()[:, 0]
+    x64 = np.linalg.solve(case.A, case.b[:, 0])
+    if kind == "getrf":
+        x32 = sl.lu_solve(sl.lu_factor(case.A.astype(np.float32)), case.b[:, 0].astype(np.float32))
+    else:
+        x32 = sl.cho_solve(sl.cho_factor(case.A.astype(np.float32), lower=True),
+                           case.b[:, 0].astype(np.float32))
+    err = float(np.linalg.norm(x - x64) / np.linalg.norm(x64))
+    err32 = float(np.linalg.norm(x32.astype(np.float64) - x64) / np.linalg.norm(x64))
+    return {
+        "metric": f"Posit32 R{kind} + R{kind[:3]}rs Gpops/s (factor {'2' if kind == 'getrf' else '1'}n^3/3 pops)",
+        "value": round(pops / (ms_per_step * 1e-3) / 1e9, 3),
+        "unit": "Gpops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "posit32 (int32 VALU)", "data": "synthetic",
+        "config": {"workload": case.name, "n": n, "nb": args.nb, "nrhs": 1,
+                   "factor_solve_ms_events": round(kms, 3), "info": int(info.cpu().item()),
+                   "forward_error_posit32": err, "forward_error_binary32": err32,
+                   "digits_gained_vs_binary32": round(float(np.log10(err32 / err)), 3)},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def to_device_patterns(mat, dev):
     """FP64 values -> Posit(32,2) patterns with the library's own conversion;
     the sprinkled special values are then set by index."""
@@ -134,7 +203,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="square_n8192")
+    ap.add_argument("--workload", default="square_n8192",
+                    help="square_nN | trailing_jJ | uniform_nN (Rgemm), getrf_nN | potrf_nN (factor+solve)")
+    ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -159,6 +230,10 @@ def main() -> int:
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return 0
+
+    if args.workload.startswith(("getrf_n", "potrf_n")):
+        print(json.dumps(run_solve_bench(args.workload, args, dev)))
         return 0
 
     case = make_case(args.workload)

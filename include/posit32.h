@@ -106,6 +106,58 @@ enum { P32_OP_ADD = 0, P32_OP_SUB = 1, P32_OP_MUL = 2, P32_OP_DIV = 3, P32_OP_SQ
 int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
                         const posit32_t* b, posit32_t* out);
 
+/*
+ * Blocked factorisations and solves (paper, Section 3: LAPACK's iterative
+ * Level-3 LU and Cholesky, MPLAPACK's Rgetrf/Rpotrf, with the solves
+ * Rgetrs/Rpotrs of Section 5.1).  Square n x n matrices, row-major, block
+ * size 1 <= nb <= 256 (the trailing updates run on posit32_gemm).  The order
+ * of every rounded operation (and so every result bit) is fixed:
+ *
+ * posit32_getrf -- P A = L U with partial pivoting, in place (unit L below the
+ *   diagonal, U on and above).  Per panel [j, j+jb): for each column c, the
+ *   pivot is argmax_{i>=c} |A[i][c]| in posit order (signed-integer order of
+ *   the patterns, |NaR| smallest), ties to the smallest i; rows c and pivot
+ *   are swapped inside the panel; A[i][c] = A[i][c] / A[c][c] for i > c
+ *   unless the pivot is 0 (then info = c+1 for the first such c and no
+ *   scaling); A[i][q] = A[i][q] - rnd(A[i][c]*A[c][q]) for i > c, c < q < j+jb.
+ *   Then the interchanges go to the other columns; U12 = L11^-1 A12 column
+ *   by column (ascending c); A22 = Rgemm(alpha = -1, beta = 1, L21, U12).
+ *   ipiv: device int32[n], 0-based (row c was swapped with row ipiv[c]).
+ *   info: device int32[1], 0 or the 1-based column of the first zero pivot.
+ * posit32_getrs -- solve A X = B with the output of posit32_getrf; B is n x
+ *   nrhs (ldb >= nrhs), overwritten by X.  Interchanges in order; forward
+ *   L (unit): for c ascending, rows r > c get B[r] - rnd(L[r][c]*B[c]);
+ *   backward U: for c descending, B[c] = B[c] / U[c][c], then rows r < c get
+ *   B[r] - rnd(U[r][c]*B[c]).
+ * posit32_potrf -- A = L L^T (lower), in place in the lower triangle; the
+ *   strict upper triangle is neither read nor written.  Per diagonal block:
+ *   for each column c: if A[c][c] <= 0 or NaR, info = c+1 and the call stops
+ *   (later blocks are not touched); A[c][c] = sqrt(A[c][c]); the block's
+ *   rows below are divided by it; the block's lower triangle gets
+ *   A[i][q] - rnd(A[i][c]*A[q][c]).  Then L21 = A21 L11^-T row by row
+ *   (ascending columns, division by L[c][c]), and the lower triangle of
+ *   A22 = Rgemm(-1, 1, L21, L21^T).
+ * posit32_potrs -- solve A X = B with the output of posit32_potrf: forward L
+ *   (for c ascending: B[c] = B[c] / L[c][c], rows below get
+ *   B[r] - rnd(L[r][c]*B[c])), then backward L^T (for c descending:
+ *   B[c] = B[c] / L[c][c], rows above get B[r] - rnd(L[c][r]*B[c])).
+ *
+ * All pointers are device memory; calls are stream-ordered and asynchronous
+ * (info is written on the device).  posit32_getrf takes a stream-ordered
+ * temporary of 8n bytes (hipMallocAsync) for its pivot search.
+ * Errors: -2 n < 0; -3 nb outside [1, 256] (getrf/potrf) or nrhs < 0
+ * (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
+ * pointer/leading-dimension arguments in order (-6, -7, ...).
+ */
+int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                  int32_t* ipiv, int32_t* info);
+int posit32_getrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
+                  const int32_t* ipiv, posit32_t* B, int64_t ldb);
+int posit32_potrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                  int32_t* info);
+int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
+                  posit32_t* B, int64_t ldb);
+
 #ifdef __cplusplus
 }
 #endif

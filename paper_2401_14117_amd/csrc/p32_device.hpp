@@ -339,3 +339,66 @@ __device__ inline win mul_slow(int32_t a8, int32_t sca, int32_t b4, int32_t scb)
 __device__ inline win add_slow(win a, win b) { return win_of(add_general(a, b)); }
 
 }  // namespace p32
+
+namespace p32 {
+
+// ---------------------------------------------------------------------------
+// pattern-level operations for the factorisation and solve kernels
+// ---------------------------------------------------------------------------
+
+// Pattern of an exactly representable window-form value.  Scales with f_s >= 1
+// are encoded directly (regime run, terminator, two exponent bits, the top f_s
+// fraction bits); others go through the general rounding.
+__device__ inline uint32_t encode_win(win w) {
+  if (w.h == 0) return 0u;
+  const bool neg = w.h < 0;
+  uint32_t mag = (uint32_t)(neg ? -w.h : w.h);
+  int sc = w.e;
+  if (mag >= (1u << 28)) { mag >>= 1; sc += 1; }   // 2^(e+1) held as 2^28
+  if (!scale_ok(sc)) return encode_exact(w);
+  const int k = sc >> 2, e = sc & 3;
+  const int R = k >= 0 ? k + 2 : 1 - k;           // run + terminator
+  const uint32_t regime = k >= 0 ? (0x7FFFFFFFu >> (30 - k)) << (30 - k) : (1u << (30 + k));
+  const uint32_t frac = mag - (1u << 27);
+  const uint32_t p = regime | ((uint32_t)e << (29 - R)) | (frac >> (R - 2));
+  return neg ? 0u - p : p;
+}
+
+// rnd(x * y) in window form, fast path with exact fallback
+__device__ inline win mul_win(dec x, dec y) {
+  win r;
+  if (x.s != 0 && y.s != 0 && mul_fast(x.s * 8, x.sc, y.s * 4, y.sc, r)) return r;
+  return win_of(mul_general(x, y));
+}
+
+// rnd(a + b) of two window-form values, fast path with exact fallback
+__device__ inline win add_win(win a, win b) {
+  win r;
+  if (add_fast(a, b, r)) return r;
+  return win_of(add_general(a, b));
+}
+
+// rnd(a - rnd(b * c)) on patterns
+__device__ inline uint32_t p_fms(uint32_t a, uint32_t b, uint32_t c) {
+  if (a == kNaR || b == kNaR || c == kNaR) return kNaR;
+  win pr = mul_win(decode(b), decode(c));
+  pr.h = -pr.h;
+  return encode_win(add_win(win_of(a), pr));
+}
+
+__device__ inline uint32_t p_div(uint32_t a, uint32_t b) {
+  return div_general(decode(a), decode(b), a == kNaR, b == kNaR);
+}
+
+__device__ inline uint32_t p_sqrt(uint32_t a) { return sqrt_general(decode(a), a == kNaR); }
+
+// key of |x| for pivot search: posit order is signed-integer order of the
+// patterns and |NaR| = NaR is the smallest; ties prefer the smaller row
+__device__ __forceinline__ unsigned long long pivot_key(uint32_t x, int64_t row) {
+  const int32_t s = (int32_t)x;
+  const int32_t a = x == kNaR ? INT32_MIN : (s < 0 ? -s : s);
+  return ((unsigned long long)((uint32_t)a ^ 0x80000000u) << 32) |
+         (unsigned long long)(0xFFFFFFFFu - (uint32_t)row);
+}
+
+}  // namespace p32

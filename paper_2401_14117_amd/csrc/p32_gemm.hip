@@ -177,11 +177,15 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
     for (int j = 0; j < TN; ++j) acc[i][j] = nacc[i][j];
 }
 
-template <bool TA, bool TB>
+// LOWER: only the lower triangle (row >= column) of C is computed and written
+// (the trailing update of a Cholesky factorisation).  skip: when non-null and
+// nonzero on entry, the kernel does nothing (a failed factorisation step).
+template <bool TA, bool TB, bool LOWER>
 __global__ void __launch_bounds__(NT, P32_GEMM_MIN_WAVES)
 gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
             const uint32_t* __restrict__ B, int64_t ldb, uint32_t* __restrict__ C, int64_t ldc,
-            uint32_t alpha, uint32_t beta) {
+            uint32_t alpha, uint32_t beta, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   __shared__ int2 As[BK][BM];   // (s << 3, scale + EB + 4) of op(A)(i0 + i, p0 + p)
   __shared__ int2 Bs[BK][BN];   // (s << 2, scale) of op(B)(p0 + p, j0 + j)
   __shared__ uint2 lut[256];    // rounding parameters of scales -128..127
@@ -205,6 +209,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
   const unsigned in_group = g % per_group;
   const int64_t i0 = (int64_t)(first_row + in_group % rows_here) * BM;
   const int64_t j0 = (int64_t)(in_group / rows_here) * BN;
+  if (LOWER && i0 + BM - 1 < j0) return;          // tile entirely above the diagonal
   if (tid < BM) rowNaR[tid] = 0;
   if (tid < BN) colNaR[tid] = 0;
   lut[tid] = round_params(tid - 128);   // NT == 256 entries
@@ -287,7 +292,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int64_t gj = j0 + tx * TN + j;
-      if (gj >= n) continue;
+      if (gj >= n || (LOWER && gj > gi)) continue;
       const int nar = rowNaR[ty * TM + i] | colNaR[tx * TN + j];
       const uint32_t c = beta ? C[gi * ldc + gj] : 0u;
       C[gi * ldc + gj] = gemm_epilogue(unbias(acc[i][j]), nar, alpha, beta, c);
@@ -297,36 +302,52 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
 
 // alpha == 0 or k == 0: C = (beta == 0) ? 0 : beta*C
 __global__ void scale_c_kernel(int64_t m, int64_t n, uint32_t* __restrict__ C, int64_t ldc,
-                               uint32_t beta) {
+                               uint32_t beta, bool lower, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * n) return;
   const int64_t i = idx / n, j = idx % n;
+  if (lower && j > i) return;
   uint32_t& c = C[i * ldc + j];
   if (beta == 0u) { c = 0u; return; }
   if (beta == kNaR || c == kNaR) { c = kNaR; return; }
   c = mul_general(decode(beta), decode(c));
 }
 
-int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
-                const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
-                uint32_t* C, int64_t ldc) {
+int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+                   const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
+                   uint32_t* C, int64_t ldc, bool lower, const int32_t* skip) {
   if (m == 0 || n == 0) return 0;
   if (alpha == 0u || k == 0) {
     const int64_t total = m * n;
     const int threads = 256;
     const int64_t blocks = (total + threads - 1) / threads;
-    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, m, n, C, ldc, beta);
+    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, m, n, C, ldc, beta,
+                       lower, skip);
     return launch_status();
   }
   const int64_t tiles = ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
   if (tiles * NT >= ((int64_t)1 << 32)) return -4;   // beyond one 1-D launch
   const dim3 grid((unsigned)tiles);
   const dim3 block(NT);
-  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<false, false>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha, beta);
-  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<false, true>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha, beta);
-  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<true, false>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha, beta);
-  else hipLaunchKernelGGL((gemm_kernel<true, true>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha, beta);
+#define P32_LAUNCH(TA_, TB_, LO_) \
+  hipLaunchKernelGGL((gemm_kernel<TA_, TB_, LO_>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, \
+                     ldc, alpha, beta, skip)
+  if (lower) {
+    if (!ta && tb) P32_LAUNCH(false, true, true);
+    else return -1;                                   // only the Cholesky form is needed
+  } else if (!ta && !tb) P32_LAUNCH(false, false, false);
+  else if (!ta && tb) P32_LAUNCH(false, true, false);
+  else if (ta && !tb) P32_LAUNCH(true, false, false);
+  else P32_LAUNCH(true, true, false);
+#undef P32_LAUNCH
   return launch_status();
+}
+
+int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+                const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
+                uint32_t* C, int64_t ldc) {
+  return launch_gemm_ex(s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, false, nullptr);
 }
 
 }  // namespace p32

@@ -15,9 +15,20 @@ inline int launch_status() {
 int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
                 const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
                 uint32_t* C, int64_t ldc);
+int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+                   const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
+                   uint32_t* C, int64_t ldc, bool lower, const int32_t* skip);
 int launch_from_f64(hipStream_t s, int64_t n, const double* x, uint32_t* out);
 int launch_to_f64(hipStream_t s, int64_t n, const uint32_t* p, double* out);
 int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, const uint32_t* b,
                        uint32_t* out);
+
+int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                 int32_t* info);
+int launch_getrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+                 const int32_t* ipiv, uint32_t* B, int64_t ldb);
+int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info);
+int launch_potrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint32_t* B,
+                 int64_t ldb);
 
 }  // namespace p32

@@ -48,7 +48,12 @@ def lib() -> ctypes.CDLL:
     L.posit32_from_f64.argtypes = [vp, i64, vp, vp]
     L.posit32_to_f64.argtypes = [vp, i64, vp, vp]
     L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
-    for f in (L.posit32_from_f64, L.posit32_to_f64, L.posit32_elementwise):
+    L.posit32_getrf.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.posit32_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64]
+    L.posit32_potrf.argtypes = [vp, i64, i64, vp, i64, vp]
+    L.posit32_potrs.argtypes = [vp, i64, i64, vp, i64, vp, i64]
+    for f in (L.posit32_from_f64, L.posit32_to_f64, L.posit32_elementwise, L.posit32_getrf,
+              L.posit32_getrs, L.posit32_potrf, L.posit32_potrs):
         f.restype = i32
     _lib = L
     return L
@@ -142,3 +147,55 @@ def elementwise(op: int, a: torch.Tensor, b: torch.Tensor | None = None, stream=
 
 def version() -> int:
     return lib().posit32_version()
+
+
+def _square(A: torch.Tensor) -> int:
+    _is_i32_cuda(A)
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    return A.shape[0]
+
+
+def _rhs(B: torch.Tensor, n: int) -> torch.Tensor:
+    _is_i32_cuda(B)
+    if B.dim() == 1:
+        B = B.view(-1, 1)
+    if B.shape[0] != n:
+        raise ValueError("right-hand side has the wrong number of rows")
+    return B
+
+
+def getrf(A: torch.Tensor, nb: int = 256, stream=None):
+    """In place LU with partial pivoting; returns (A, ipiv, info) with ipiv an
+    int32 device tensor (0-based) and info a 1-element int32 device tensor."""
+    n = _square(A)
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib().posit32_getrf(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(ipiv), _ptr(info)),
+           "posit32_getrf")
+    return A, ipiv[:n], info
+
+
+def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """In place solve with the output of getrf; B is n x nrhs (or length n)."""
+    n = _square(LU)
+    B2 = _rhs(B, n)
+    _check(lib().posit32_getrs(_stream(stream), n, B2.shape[1], _ptr(LU), _ld(LU), _ptr(ipiv),
+                               _ptr(B2), _ld(B2)), "posit32_getrs")
+    return B
+
+
+def potrf(A: torch.Tensor, nb: int = 256, stream=None):
+    """In place lower Cholesky; returns (A, info)."""
+    n = _square(A)
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    _check(lib().posit32_potrf(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(info)), "posit32_potrf")
+    return A, info
+
+
+def potrs(L: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    n = _square(L)
+    B2 = _rhs(B, n)
+    _check(lib().posit32_potrs(_stream(stream), n, B2.shape[1], _ptr(L), _ld(L), _ptr(B2), _ld(B2)),
+           "posit32_potrs")
+    return B

@@ -1,0 +1,137 @@
+"""GPU parity of the blocked factorisations and solves against the oracle,
+bit for bit (factors, pivots, info and solutions)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_14117_amd import workloads as W
+from tests.helpers import from_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+NAR = 0x80000000
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2401_14117_amd import posit32
+    posit32.lib()
+    return posit32
+
+
+def p32(x):
+    return O.vec_from_double(np.asarray(x, dtype=np.float64))
+
+
+def _gpu_getrf(P, A, nb):
+    import torch
+    Ad = to_dev(A)
+    _, ipiv, info = P.getrf(Ad, nb)
+    torch.cuda.synchronize()
+    return from_dev(Ad), ipiv.cpu().numpy(), int(info.cpu().item())
+
+
+def _gpu_potrf(P, A, nb):
+    import torch
+    Ad = to_dev(A)
+    _, info = P.potrf(Ad, nb)
+    torch.cuda.synchronize()
+    return from_dev(Ad), int(info.cpu().item())
+
+
+def _diff(a, b):
+    bad = np.argwhere(a != b)
+    return [(tuple(i), hex(a[tuple(i)]), hex(b[tuple(i)])) for i in bad[:6]]
+
+
+@pytest.mark.parametrize("n,nb", [(1, 256), (5, 256), (64, 256), (255, 256), (257, 256), (300, 64),
+                                  (300, 256), (520, 256), (130, 1)])
+def test_getrf_getrs_parity(P, n, nb):
+    rng = np.random.default_rng(n * 31 + nb)
+    A = p32(rng.uniform(-1, 1, (n, n)) * 2.0 ** rng.integers(-3, 4, (n, n)))
+    LU, ipiv, info = O.getrf(A, nb)
+    gLU, gipiv, ginfo = _gpu_getrf(P, A, nb)
+    assert np.array_equal(gipiv, ipiv)
+    assert ginfo == info
+    assert np.array_equal(gLU, LU), _diff(gLU, LU)
+    B = p32(rng.uniform(-1, 1, (n, 3)))
+    X = O.getrs(LU, ipiv, B)
+    import torch
+    Bd = to_dev(B)
+    P.getrs(to_dev(LU), torch.from_numpy(ipiv).cuda(), Bd)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+
+
+def test_getrf_singular_and_nar(P):
+    rng = np.random.default_rng(3)
+    A = rng.uniform(-1, 1, (40, 40))
+    A[:, 7] = 0.0
+    A[:, 30] = 0.0
+    Ap = p32(A)
+    Ap[12, 20] = NAR
+    LU, ipiv, info = O.getrf(Ap, 16)
+    gLU, gipiv, ginfo = _gpu_getrf(P, Ap, 16)
+    assert info == 8 and ginfo == 8
+    assert np.array_equal(gipiv, ipiv)
+    assert np.array_equal(gLU, LU), _diff(gLU, LU)
+
+
+@pytest.mark.parametrize("n,nb", [(1, 256), (7, 256), (100, 256), (256, 256), (300, 64), (300, 256),
+                                  (520, 256), (77, 1)])
+def test_potrf_potrs_parity(P, n, nb):
+    case = W.chol_case(n, nrhs=2)
+    A = p32(case.A)
+    L, info = O.potrf(A, nb)
+    gL, ginfo = _gpu_potrf(P, A, nb)
+    assert ginfo == info == 0
+    assert np.array_equal(gL, L), _diff(gL, L)
+    X = O.potrs(L, p32(case.b))
+    Bd = to_dev(p32(case.b))
+    P.potrs(to_dev(L), Bd)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+
+
+@pytest.mark.parametrize("bad", [5, 300, 511])
+def test_potrf_not_positive_definite(P, bad):
+    n = 520
+    case = W.chol_case(n)
+    A = case.A.copy()
+    A[bad, bad] = -50.0
+    Ap = p32(A)
+    L, info = O.potrf(Ap, 256)
+    gL, ginfo = _gpu_potrf(P, Ap, 256)
+    assert ginfo == info and info > 0
+    assert np.array_equal(gL, L), _diff(gL, L)
+
+
+def test_exact_recovery_on_gpu(P):
+    """Dyadic L*U with pivot-preserving |L| < 1, rows shuffled: the GPU
+    returns the exact factors (closed form, independent of the oracle)."""
+    n = 300
+    rng = np.random.default_rng(8)
+    L = np.tril(rng.choice([0.0, 0.5, -0.5, 0.25, -0.25], (n, n)), -1) + np.eye(n)
+    U = np.triu(rng.integers(-3, 4, (n, n)).astype(float), 1) + np.diag(rng.choice([1.0, -2.0, 4.0], n))
+    A = (L @ U)[rng.permutation(n)]
+    gLU, gipiv, ginfo = _gpu_getrf(P, p32(A), 64)
+    assert ginfo == 0
+    got = O.vec_to_double(gLU)
+    assert np.array_equal(np.tril(got, -1), np.tril(L, -1))
+    assert np.array_equal(np.triu(got), U)
+
+
+@pytest.mark.parametrize("kind", ["lu", "chol"])
+def test_n768_parity(P, kind):
+    n = 768
+    if kind == "lu":
+        case = W.lu_case(n)
+        A = p32(case.A)
+        LU, ipiv, info = O.getrf(A, 256)
+        gLU, gipiv, ginfo = _gpu_getrf(P, A, 256)
+        assert np.array_equal(gipiv, ipiv) and ginfo == info
+        assert np.array_equal(gLU, LU), _diff(gLU, LU)
+    else:
+        case = W.chol_case(n)
+        A = p32(case.A)
+        L, info = O.potrf(A, 256)
+        gL, ginfo = _gpu_potrf(P, A, 256)
+        assert ginfo == info == 0
+        assert np.array_equal(gL, L), _diff(gL, L)

@@ -72,7 +72,7 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
   if (lda < (n > 1 ? n : 1)) return -5;
   if (n > 0 && ipiv == nullptr) return -6;
   if (info == nullptr) return -7;
-  if (n >= ((int64_t)1 << 31)) return -2;
+  if (n > 0xFFFFFE) return -2;                    // pivot rows are carried in 24 bits
   return p32::launch_getrf((hipStream_t)stream, n, nb, A, lda, ipiv, info);
 }
 

@@ -133,13 +133,44 @@ __device__ inline uint32_t round_general(bool neg, unsigned __int128 M, int x, b
   return neg ? (0u - P) : P;
 }
 
+// round_general for an exact value whose integer part M fits in 64 bits
+__device__ inline uint32_t round_general64(bool neg, uint64_t M, int x, bool sticky) {
+  if (M == 0) {
+    if (!sticky) return 0u;
+    return neg ? 0xFFFFFFFFu : 1u;
+  }
+  const int t = 63 - __clzll(M);
+  const int sc = x + t;
+  uint32_t P;
+  const bool pow2 = (M & (M - 1)) == 0 && !sticky;
+  if (sc >= kMaxScale) {
+    P = kMaxpos;
+  } else if (sc < -kMaxScale || (sc == -kMaxScale && pow2)) {
+    P = 1u;
+  } else {
+    const int k = sc >> 2;
+    const int e = sc & 3;
+    const int R = k >= 0 ? k + 2 : 1 - k;
+    const uint64_t regime = k >= 0 ? ((((uint64_t)1 << (k + 1)) - 1) << 1) : (uint64_t)1;
+    const uint64_t f64 = t == 0 ? 0 : (M << (64 - t));   // fraction bits, left-aligned
+    const int fsh = R + 2;
+    bool s = sticky || (f64 & ((((uint64_t)1) << fsh) - 1)) != 0;
+    const uint64_t body = (regime << (64 - R)) | ((uint64_t)e << (62 - R)) | (f64 >> fsh);
+    P = (uint32_t)(body >> 33);
+    const bool G = (body >> 32) & 1u;
+    s = s || (uint32_t)body != 0;
+    if (G && (s || (P & 1u))) P += 1u;
+  }
+  return neg ? (0u - P) : P;
+}
+
 // exact product of two decoded operands, rounded
 __device__ inline uint32_t mul_general(dec a, dec b) {
   if (a.s == 0 || b.s == 0) return 0u;
   const bool neg = (a.s < 0) != (b.s < 0);
   const uint64_t ma = (uint64_t)(a.s < 0 ? -(int64_t)a.s : a.s);
   const uint64_t mb = (uint64_t)(b.s < 0 ? -(int64_t)b.s : b.s);
-  return round_general(neg, (unsigned __int128)(ma * mb), a.sc + b.sc - 54, false);
+  return round_general64(neg, ma * mb, a.sc + b.sc - 54, false);
 }
 
 // pattern of a window-form value that is exactly representable
@@ -147,7 +178,7 @@ __device__ inline uint32_t encode_exact(win a) {
   if (a.h == 0) return 0u;
   const bool neg = a.h < 0;
   const uint64_t m = (uint64_t)(neg ? -(int64_t)a.h : a.h);
-  return round_general(neg, m, a.e - 27, false);
+  return round_general64(neg, m, a.e - 27, false);
 }
 
 // exact sum of two window-form values (each exactly a posit), rounded
@@ -184,8 +215,8 @@ __device__ inline uint32_t add_general(win a, win b) {
 __device__ inline win win_of(uint32_t p) { return to_win(decode(p)); }
 
 // ---------------------------------------------------------------------------
-// division and square root (long division / digit-by-digit square root, with
-// the remainder as the sticky bit)
+// division and square root: exact integer quotient / integer square root
+// (from a binary64 estimate corrected in integers), the remainder as sticky
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t div_general(dec a, dec b, bool a_nar, bool b_nar) {
   if (a_nar || b_nar || b.s == 0) return kNaR;
@@ -193,9 +224,14 @@ __device__ inline uint32_t div_general(dec a, dec b, bool a_nar, bool b_nar) {
   const bool neg = (a.s < 0) != (b.s < 0);
   const uint64_t ma = (uint64_t)(a.s < 0 ? -(int64_t)a.s : a.s);
   const uint64_t mb = (uint64_t)(b.s < 0 ? -(int64_t)b.s : b.s);
-  const uint64_t num = ma << 36;                 // < 2^64
-  const uint64_t q = num / mb, r = num % mb;     // q >= 2^35
-  return round_general(neg, q, a.sc - b.sc - 36, r != 0);
+  const uint64_t num = ma << 36;                 // < 2^64, exact in binary64
+  // Quotient estimate from a binary64 division (within 2^-16 of num/mb,
+  // which is below 2^37), then the exact floor and remainder in integers.
+  uint64_t q = (uint64_t)((double)num / (double)mb);
+  int64_t r = (int64_t)(num - q * mb);           // |r| < 2 mb
+  if (r < 0) { q -= 1; r += (int64_t)mb; }
+  else if (r >= (int64_t)mb) { q += 1; r -= (int64_t)mb; }
+  return round_general64(neg, q, a.sc - b.sc - 36, r != 0);
 }
 
 __device__ inline uint32_t sqrt_general(dec a, bool a_nar) {
@@ -204,16 +240,12 @@ __device__ inline uint32_t sqrt_general(dec a, bool a_nar) {
   uint64_t m = (uint64_t)a.s;
   int x = a.sc - 27;                             // a = m * 2^x
   if (x & 1) { m <<= 1; x -= 1; }
-  const uint64_t v = m << 34;                    // < 2^63, even shift
-  uint64_t r = 0, bit = (uint64_t)1 << 62;
-  uint64_t rem = v;
-  while (bit > rem) bit >>= 2;
-  while (bit) {
-    if (rem >= r + bit) { rem -= r + bit; r = (r >> 1) + bit; }
-    else { r >>= 1; }
-    bit >>= 2;
-  }
-  return round_general(false, r, x / 2 - 17, rem != 0);
+  const uint64_t v = m << 34;                    // < 2^63, at most 29 significant bits
+  // integer square root: binary64 estimate (within one unit), then exact fix-up
+  uint64_t r = (uint64_t)sqrt((double)v);
+  if (r * r > v) r -= 1;
+  else if ((r + 1) * (r + 1) <= v) r += 1;
+  return round_general64(false, r, x / 2 - 17, v != r * r);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,12 +410,17 @@ __device__ inline win add_win(win a, win b) {
   return win_of(add_general(a, b));
 }
 
-// rnd(a - rnd(b * c)) on patterns
-__device__ inline uint32_t p_fms(uint32_t a, uint32_t b, uint32_t c) {
+// rnd(a - rnd(b * c)), with b and c given as patterns and already decoded
+__device__ inline uint32_t p_fms_pre(uint32_t a, uint32_t b, dec db, uint32_t c, dec dc) {
   if (a == kNaR || b == kNaR || c == kNaR) return kNaR;
-  win pr = mul_win(decode(b), decode(c));
+  win pr = mul_win(db, dc);
   pr.h = -pr.h;
   return encode_win(add_win(win_of(a), pr));
+}
+
+// rnd(a - rnd(b * c)) on patterns
+__device__ inline uint32_t p_fms(uint32_t a, uint32_t b, uint32_t c) {
+  return p_fms_pre(a, b, decode(b), c, decode(c));
 }
 
 __device__ inline uint32_t p_div(uint32_t a, uint32_t b) {

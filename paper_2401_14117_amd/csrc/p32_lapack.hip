@@ -34,12 +34,12 @@ constexpr uint32_t kMinusOne = 0xC0000000u;
 
 // ---- LU panel --------------------------------------------------------------
 
-__device__ inline void wave_atomic_max(unsigned long long* dst, unsigned long long v) {
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long o = __shfl_xor(v, off);
     v = o > v ? o : v;
   }
-  if ((threadIdx.x & 63) == 0 && v != 0ull) atomicMax(dst, v);
+  return v;
 }
 
 // v[u] for a wave-uniform u in 0..3, without dynamic register indexing
@@ -53,63 +53,199 @@ __device__ __forceinline__ void put4(uint32_t (&v)[4], int u, uint32_t x) {
   else v[3] = x;
 }
 
-// pivot key of column c over rows [c, n)
-__global__ void argmax_kernel(const uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t c,
-                              unsigned long long* __restrict__ key) {
-  unsigned long long best = 0ull;
-  for (int64_t i = c + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long kk = pivot_key(A[i * lda + c], i);
-    best = kk > best ? kk : best;
-  }
-  wave_atomic_max(key, best);
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelLds = 16384;        // words of panel rows a workgroup keeps in LDS
+constexpr unsigned kPollLimit = 1u << 20;
+
+// Pivot slot of one workgroup for column c: [63:32] the |value| key of its
+// best candidate (see pivot_key), [31:8] 0xFFFFFF - row (ties to the smaller
+// row), [7:0] c mod 256 as the step tag; 0 in [63:8] means "no candidate".
+//
+// Everything one workgroup publishes for another (slots and row copies) is
+// written and read with agent-scope relaxed atomics, which on gfx950 go to
+// the device-coherent level of the memory hierarchy instead of a compute
+// unit's or an XCD's private caches.  A workgroup writes its row copies,
+// waits until its stores are acknowledged (s_waitcnt), joins a workgroup
+// barrier, and only then writes its slot; a reader issues its copy loads
+// only after it has seen every slot with the current tag.  Agent-scope
+// fences would give the same ordering but write back and invalidate the
+// whole L2 on every column step, which costs ten times more.
+__device__ __forceinline__ void publish_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t read_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// record the pivot of column c and swap rows c and p inside the panel
-__global__ void panel_swap_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t c,
-                                  int64_t j, int64_t jb, const unsigned long long* __restrict__ key,
-                                  int32_t* __restrict__ ipiv, int32_t* __restrict__ info) {
-  const unsigned long long kc = key[c];
-  int64_t p = (int64_t)(0xFFFFFFFFu - (uint32_t)(kc & 0xFFFFFFFFull));
-  if (kc == 0ull || p < c || p >= n) p = c;       // (a search always sets the key)
-  const uint32_t abs_pivot = (uint32_t)(kc >> 32) ^ 0x80000000u;   // |pivot| pattern
+__device__ __forceinline__ unsigned long long pivot_slot(uint32_t x, int64_t row, int64_t c) {
+  const unsigned long long k = pivot_key(x, row) >> 32;
+  return (k << 32) | ((unsigned long long)((0xFFFFFFu - (uint32_t)row) & 0xFFFFFFu) << 8) |
+         (unsigned long long)(c & 0xFF);
+}
+__device__ __forceinline__ int64_t slot_row(unsigned long long v) {
+  return (int64_t)(0xFFFFFFu - (uint32_t)((v >> 8) & 0xFFFFFFu));
+}
+
+// Factorisation of the panel A[j:n, j:j+jb] by one cooperative launch (all
+// workgroups resident).  Workgroup w owns the R consecutive rows starting at
+// j + w R (in LDS when they fit, else in place in A).  Per column c:
+//   1. every workgroup publishes its best pivot candidate for column c: a
+//      copy of the whole panel row, then its slot; the owner of row c also
+//      publishes a copy of row c;
+//   2. every workgroup waits until all slots carry the tag of column c (this
+//      is the only grid-wide synchronisation) and takes the largest;
+//   3. the owners of rows c and p swap them from the published copies, and
+//      each workgroup scales column c and applies the rank-1 update to its
+//      rows below c.
+// Other workgroups' rows are only read from the published copies; copies and
+// slots are double-buffered by the parity of c (a workgroup can be at most
+// one column ahead of any other).  A wait that exceeds kPollLimit rounds
+// gives up: info is set to -1 and the workgroup exits, so no wave can wait
+// forever.  Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb].
+template <bool LDS>
+__global__ void __launch_bounds__(kPanelThreads)
+lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int jb, int R,
+                unsigned long long* __restrict__ slot, uint32_t* __restrict__ crow,
+                uint32_t* __restrict__ rowc, int32_t* __restrict__ ipiv, int32_t* __restrict__ info) {
+  __shared__ uint32_t tile[LDS ? kPanelLds : 1];
+  __shared__ uint32_t urow[kMaxNB], orow[kMaxNB];
+  __shared__ dec udec[kMaxNB];
+  __shared__ unsigned long long red[kPanelThreads / 64];
+  __shared__ unsigned long long sbest;
+
   const int t = threadIdx.x;
-  if (t == 0) {
-    ipiv[c] = (int32_t)p;
-    if (abs_pivot == 0u && *info == 0) *info = (int32_t)(c + 1);
-  }
-  if (p != c && t < jb) {
-    const int64_t q = j + t;
-    const uint32_t x = A[c * lda + q];
-    A[c * lda + q] = A[p * lda + q];
-    A[p * lda + q] = x;
-  }
-}
+  const unsigned G = gridDim.x;
+  const unsigned w = blockIdx.x;
+  const int64_t r0 = j + (int64_t)w * R;
+  const int nr = (int)min((int64_t)R, n - r0);   // >= 1 by the host's choice of G
+  uint32_t* T = LDS ? tile : A + r0 * lda + j;
+  const int64_t ts = LDS ? jb : lda;              // row stride of T
 
-// rows (c, n): scale column c by the pivot, rank-1 update of the panel
-// columns (c, j+jb), and the pivot key of column c+1
-__global__ void __launch_bounds__(256)
-panel_update_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t c, int64_t j,
-                    int64_t jb, unsigned long long* __restrict__ key) {
-  __shared__ uint32_t urow[kMaxNB];
-  const int64_t qend = j + jb;
-  const int64_t w = qend - c - 1;                 // columns to update
-  for (int64_t t = threadIdx.x; t < w; t += blockDim.x) urow[t] = A[c * lda + c + 1 + t];
-  __syncthreads();
-  const uint32_t piv = A[c * lda + c];
-  unsigned long long best = 0ull;
-  const int64_t i = c + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    uint32_t* row = A + i * lda;
-    uint32_t l = row[c];
-    if (piv != 0u) {
-      l = p_div(l, piv);
-      row[c] = l;
+  if (LDS) {
+    for (int idx = t; idx < nr * jb; idx += kPanelThreads) {
+      const int rr = idx / jb, q = idx - rr * jb;
+      tile[idx] = A[(r0 + rr) * lda + j + q];
     }
-    for (int64_t t = 0; t < w; ++t) row[c + 1 + t] = p_fms(row[c + 1 + t], l, urow[t]);
-    if (w > 0) best = pivot_key(row[c + 1], i);
+    __syncthreads();
   }
-  if (w > 0) wave_atomic_max(key + c + 1, best);
+
+  // largest value over the threads of the workgroup, returned to all of them
+  auto block_max = [&](unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(v, off);
+      v = o > v ? o : v;
+    }
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long b = red[0];
+      for (int i = 1; i < kPanelThreads / 64; ++i) b = red[i] > b ? red[i] : b;
+      sbest = b;
+    }
+    __syncthreads();
+    return sbest;
+  };
+
+  // step 1 for column c
+  auto publish = [&](int64_t c) {
+    const int cl = (int)(c - j);
+    const int par = (int)(c & 1);
+    unsigned long long best = 0ull;
+    for (int rr = t; rr < nr; rr += kPanelThreads)
+      if (r0 + rr >= c) {
+        const unsigned long long v = pivot_slot(T[rr * ts + cl], r0 + rr, c);
+        best = v > best ? v : best;
+      }
+    best = block_max(best);
+    if ((best >> 8) != 0ull) {
+      const int rr = (int)(slot_row(best) - r0);
+      uint32_t* dst = crow + ((size_t)par * G + w) * jb;
+      for (int q = t; q < jb; q += kPanelThreads) publish_u32(dst + q, T[rr * ts + q]);
+    }
+    if (c >= r0 && c < r0 + nr)
+      for (int q = t; q < jb; q += kPanelThreads)
+        publish_u32(rowc + (size_t)par * jb + q, T[(c - r0) * ts + q]);
+    __builtin_amdgcn_s_waitcnt(0);                // this wave's copies are acknowledged
+    __syncthreads();
+    if (t == 0) {
+      const unsigned long long v = (best >> 8) != 0ull ? best : (unsigned long long)(c & 0xFF);
+      __hip_atomic_store(&slot[(size_t)par * G + w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+
+  // step 2 for column c: the winning slot, or 0 after a time-out
+  auto await = [&](int64_t c) -> unsigned long long {
+    const int par = (int)(c & 1);
+    const unsigned long long tag = (unsigned long long)(c & 0xFF);
+    unsigned long long mine = 0ull;
+    for (unsigned rounds = 0;; ++rounds) {
+      int ok = 1;
+      mine = 0ull;
+      for (unsigned g = t; g < G; g += kPanelThreads) {
+        const unsigned long long v =
+            __hip_atomic_load(&slot[(size_t)par * G + g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((v & 0xFFull) != tag) ok = 0;
+        mine = v > mine ? v : mine;
+      }
+      if (__syncthreads_and(ok)) break;
+      if (rounds >= kPollLimit) return 0ull;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    return block_max(mine);
+  };
+
+  for (int cl = 0; cl < jb; ++cl) {
+    const int64_t c = j + cl;
+    const int par = (int)(c & 1);
+    publish(c);
+    const unsigned long long best = await(c);
+    if (best == 0ull) {
+      if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    int64_t p = slot_row(best);
+    if ((best >> 8) == 0ull || p < c || p >= n) p = c;   // (some row >= c always publishes)
+    const unsigned wp = (unsigned)((p - j) / R);
+    const bool own_c = c >= r0 && c < r0 + nr;
+    const bool own_p = p != c && p >= r0 && p < r0 + nr;
+    for (int q = t; q < jb; q += kPanelThreads) {
+      const uint32_t u = read_u32(crow + ((size_t)par * G + wp) * jb + q);
+      urow[q] = u;
+      udec[q] = decode(u);
+      if (own_p) orow[q] = read_u32(rowc + (size_t)par * jb + q);
+    }
+    __syncthreads();
+    const uint32_t piv = urow[cl];
+    if (w == 0 && t == 0) {
+      ipiv[c] = (int32_t)p;
+      if (piv == 0u && *info == 0) *info = (int32_t)(c + 1);
+    }
+    for (int q = t; q < jb; q += kPanelThreads) {
+      if (own_c) T[(c - r0) * ts + q] = urow[q];
+      if (own_p) T[(p - r0) * ts + q] = orow[q];
+    }
+    __syncthreads();
+    // rows below c: scale column c, then the rank-1 update right of it
+    const int rs = (int)max((int64_t)0, c + 1 - r0);
+    if (piv != 0u)
+      for (int rr = rs + t; rr < nr; rr += kPanelThreads) T[rr * ts + cl] = p_div(T[rr * ts + cl], piv);
+    __syncthreads();
+    const int wq = jb - cl - 1;
+    const int cnt = nr > rs ? (nr - rs) * wq : 0;
+    for (int idx = t; idx < cnt; idx += kPanelThreads) {
+      const int dr = idx / wq;
+      const int rr = rs + dr, q = cl + 1 + (idx - dr * wq);
+      const uint32_t l = T[rr * ts + cl];
+      T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+    }
+    __syncthreads();
+  }
+
+  if (LDS)
+    for (int idx = t; idx < nr * jb; idx += kPanelThreads) {
+      const int rr = idx / jb, q = idx - rr * jb;
+      A[(r0 + rr) * lda + j + q] = tile[idx];
+    }
 }
 
 // apply the interchanges of panel [j, j+jb) to the columns outside it
@@ -158,37 +294,58 @@ trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int6
 
 // ---- Cholesky --------------------------------------------------------------
 
-// unblocked Cholesky of the diagonal block [j, j+jb) in one workgroup
-__global__ void __launch_bounds__(1024)
-potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int64_t jb, int32_t* __restrict__ info) {
-  __shared__ uint32_t dsh;
+// Unblocked Cholesky of the diagonal block [j, j+jb) in one workgroup, with
+// the block's lower triangle held in LDS (row i at offset i(i+1)/2).  Each
+// column step spreads the trailing triangle c < q <= i < jb evenly over the
+// threads.  On a non-positive or NaR diagonal the block is written back as it
+// stands and info is set.
+constexpr int kTri = kMaxNB * (kMaxNB + 1) / 2;
+constexpr int kPotf2Threads = 1024;
+
+__device__ __forceinline__ int tri_off(int i) { return i * (i + 1) / 2; }
+
+__global__ void __launch_bounds__(kPotf2Threads)
+potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* __restrict__ info) {
+  __shared__ uint32_t D[kTri];
+  __shared__ uint32_t col[kMaxNB];
   __shared__ int stop;
   if (*info != 0) return;
   const int t = threadIdx.x;
-  uint32_t* D = A + j * lda + j;
-  for (int c = 0; c < jb; ++c) {
+  uint32_t* G = A + j * lda + j;
+  for (int i = t >> 6; i < jb; i += kPotf2Threads / 64)
+    for (int q = t & 63; q <= i; q += 64) D[tri_off(i) + q] = G[i * lda + q];
+  __syncthreads();
+  int c = 0;
+  for (; c < jb; ++c) {
     if (t == 0) {
-      const uint32_t a = D[c * lda + c];
+      const uint32_t a = D[tri_off(c) + c];
       stop = (int32_t)a <= 0;                     // non-positive or NaR
-      if (stop) {
-        *info = (int32_t)(j + c + 1);
-      } else {
-        dsh = p_sqrt(a);
-        D[c * lda + c] = dsh;
-      }
+      if (stop) *info = (int32_t)(j + c + 1);
+      else D[tri_off(c) + c] = p_sqrt(a);
     }
     __syncthreads();
-    if (stop) return;
-    const uint32_t d = dsh;
-    for (int i = c + 1 + t; i < jb; i += blockDim.x) D[i * lda + c] = p_div(D[i * lda + c], d);
+    if (stop) break;
+    const uint32_t d = D[tri_off(c) + c];
+    for (int r = c + 1 + t; r < jb; r += kPotf2Threads) {
+      const uint32_t x = p_div(D[tri_off(r) + c], d);
+      D[tri_off(r) + c] = x;
+      col[r] = x;
+    }
     __syncthreads();
-    // lower triangle c < q <= i < jb: 32 row lanes x 32 column lanes
-    const int ri = t >> 5, qi = t & 31;
-    for (int i = c + 1 + ri; i < jb; i += 32)
-      for (int q = c + 1 + qi; q <= i; q += 32)
-        D[i * lda + q] = p_fms(D[i * lda + q], D[i * lda + c], D[q * lda + c]);
+    // trailing triangle: local row a = i-c-1, local column b = q-c-1 <= a
+    const int m = jb - c - 1;
+    const int cnt = m * (m + 1) / 2;
+    for (int idx = t; idx < cnt; idx += kPotf2Threads) {
+      int a = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+      if (tri_off(a + 1) <= idx) ++a;
+      if (tri_off(a) > idx) --a;
+      const int i = c + 1 + a, q = c + 1 + (idx - tri_off(a));
+      D[tri_off(i) + q] = p_fms(D[tri_off(i) + q], col[i], col[q]);
+    }
     __syncthreads();
   }
+  for (int i = t >> 6; i < jb; i += kPotf2Threads / 64)
+    for (int q = t & 63; q <= i; q += 64) G[i * lda + q] = D[tri_off(i) + q];
 }
 
 // L21 = A21 L11^-T: one wave per row of A21; lane t holds columns t + 64 u.
@@ -239,27 +396,61 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
   return kind == 3 ? M[c * lda + r] : M[r * lda + c];
 }
 
-// diagonal block [s, s+bs) of the solve, all right-hand sides, one workgroup
-__global__ void __launch_bounds__(256)
+// Diagonal block [s, s+bs) of the solve for the right-hand sides
+// [q0, q0+kRhsChunk) (one workgroup per chunk).  Thread r owns row s+r; the
+// block's unknowns live in LDS and the coefficients are staged in LDS 32
+// columns at a time.  Per column c (in solve order): the non-unit kinds divide
+// x[c] by the diagonal, then every later row r gets x[r] - rnd(T(r,c) x[c]).
+constexpr int kTrsvBlock = 256;
+constexpr int kRhsChunk = 4;
+constexpr int kCoefCols = 32;
+
+__global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
-                 int64_t nrhs, int64_t s, int64_t bs, int kind) {
+                 int64_t nrhs, int64_t s, int bs, int kind) {
+  __shared__ uint32_t xs[kTrsvBlock][kRhsChunk];
+  __shared__ uint32_t coef[kTrsvBlock][kCoefCols + 1];
+  __shared__ uint32_t diag[kCoefCols];
   const bool forward = kind == 0 || kind == 2;
   const bool unit = kind == 0;
   const int t = threadIdx.x;
-  for (int64_t step = 0; step < bs; ++step) {
-    const int64_t c = forward ? s + step : s + bs - 1 - step;
-    if (!unit)
-      for (int64_t q = t; q < nrhs; q += blockDim.x)
-        B[c * ldb + q] = p_div(B[c * ldb + q], M[c * lda + c]);
+  const int64_t q0 = (int64_t)blockIdx.x * kRhsChunk;
+  const int nq = (int)min((int64_t)kRhsChunk, nrhs - q0);
+  if (t < bs)
+    for (int u = 0; u < nq; ++u) xs[t][u] = B[(s + t) * ldb + q0 + u];
+  for (int step0 = 0; step0 < bs; step0 += kCoefCols) {
+    const int steps = min(kCoefCols, bs - step0);
     __syncthreads();
-    const int64_t r0 = forward ? c + 1 : s, r1 = forward ? s + bs : c;
-    const int64_t cnt = (r1 - r0) * nrhs;
-    for (int64_t idx = t; idx < cnt; idx += blockDim.x) {
-      const int64_t r = r0 + idx / nrhs, q = idx % nrhs;
-      B[r * ldb + q] = p_fms(B[r * ldb + q], tri_coef(M, lda, kind, r, c), B[c * ldb + q]);
+    // stage T(r, c) for the next columns of the solve order, c = col(step)
+    for (int idx = t; idx < bs * steps; idx += kTrsvBlock) {
+      int r, u;
+      if (kind == 3) { u = idx / bs; r = idx - u * bs; }   // row c of M is contiguous in r
+      else { r = idx / steps; u = idx - r * steps; }
+      const int64_t c = forward ? s + step0 + u : s + bs - 1 - step0 - u;
+      coef[r][u] = tri_coef(M, lda, kind, s + r, c);
     }
+    if (!unit)
+      for (int u = t; u < steps; u += kTrsvBlock) {
+        const int64_t c = forward ? s + step0 + u : s + bs - 1 - step0 - u;
+        diag[u] = M[c * lda + c];
+      }
     __syncthreads();
+    for (int u = 0; u < steps; ++u) {
+      const int cl = forward ? step0 + u : bs - 1 - step0 - u;   // local column
+      if (!unit) {
+        if (t < nq) xs[cl][t] = p_div(xs[cl][t], diag[u]);
+        __syncthreads();
+      }
+      const bool below = forward ? t > cl : t < cl;
+      if (t < bs && below) {
+        const uint32_t m = coef[t][u];
+        for (int v = 0; v < nq; ++v) xs[t][v] = p_fms(xs[t][v], m, xs[cl][v]);
+      }
+      __syncthreads();
+    }
   }
+  if (t < bs)
+    for (int u = 0; u < nq; ++u) B[(s + t) * ldb + q0 + u] = xs[t][u];
 }
 
 // rows outside the diagonal block [s, s+bs) get that block's columns, in
@@ -298,13 +489,14 @@ __global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
 
 static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32_t* B, int64_t ldb,
                 int64_t nrhs, int kind) {
-  const int64_t bsz = 256;
+  const int64_t bsz = kTrsvBlock;
   const bool forward = kind == 0 || kind == 2;
   const int64_t nblk = (n + bsz - 1) / bsz;
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t s0 = forward ? b * bsz : (nblk - 1 - b) * bsz;
     const int64_t bs = s0 + bsz < n ? bsz : n - s0;
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3(1), dim3(256), 0, s, M, lda, B, ldb, nrhs, s0, bs, kind);
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3((unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk)),
+                       dim3(kTrsvBlock), 0, s, M, lda, B, ldb, nrhs, s0, (int)bs, kind);
     const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? n : s0;
     const int64_t cnt = (r1 - r0) * nrhs;
     if (cnt > 0)
@@ -316,26 +508,63 @@ static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32
 
 // ---- drivers ---------------------------------------------------------------
 
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t count, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
 int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                  int32_t* info) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
   if (n == 0) return launch_status();
-  unsigned long long* keys = nullptr;
-  hipError_t e = hipMallocAsync((void**)&keys, (size_t)n * sizeof(unsigned long long), s);
+  int dev = 0, cus = 0, per_cu_lds = 0, per_cu_glb = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu_lds, reinterpret_cast<const void*>(&lu_panel_kernel<true>), kPanelThreads, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu_glb, reinterpret_cast<const void*>(&lu_panel_kernel<false>), kPanelThreads, 0);
   if (e != hipSuccess) return -1000 - (int)e;
-  e = hipMemsetAsync(keys, 0, (size_t)n * sizeof(unsigned long long), s);
+  if (per_cu_lds < 1 || per_cu_glb < 1) return -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+  // at most one workgroup per compute unit (and per slot-reading thread),
+  // at least 8 rows per workgroup
+  int64_t gmax = cus < 1 ? 1 : cus;
+  if (gmax > kPanelThreads) gmax = kPanelThreads;
+
+  const size_t slot_bytes = (size_t)2 * gmax * sizeof(unsigned long long);
+  const size_t row_bytes = (size_t)2 * gmax * kMaxNB * sizeof(uint32_t);
+  const size_t rowc_bytes = (size_t)2 * kMaxNB * sizeof(uint32_t);
+  char* ws = nullptr;
+  e = hipMallocAsync((void**)&ws, slot_bytes + row_bytes + rowc_bytes, s);
   if (e != hipSuccess) return -1000 - (int)e;
-  for (int64_t j = 0; j < n; j += nb) {
+  unsigned long long* slot = reinterpret_cast<unsigned long long*>(ws);
+  uint32_t* crow = reinterpret_cast<uint32_t*>(ws + slot_bytes);
+  uint32_t* rowc = reinterpret_cast<uint32_t*>(ws + slot_bytes + row_bytes);
+  // tag 0xFF matches neither column 0 nor column 1
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((2 * gmax + 255) / 256)), dim3(256), 0, s, slot,
+                     (int64_t)(2 * gmax), ~0ull);
+  int rc = launch_status();
+  for (int64_t j = 0; j < n && rc == 0; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;
-    const unsigned g0 = (unsigned)((n - j + 255) / 256);
-    hipLaunchKernelGGL(argmax_kernel, dim3(g0 < 64 ? g0 : 64), dim3(256), 0, s, A, lda, n, j, keys + j);
-    for (int64_t c = j; c < j + jb; ++c) {
-      hipLaunchKernelGGL(panel_swap_kernel, dim3(1), dim3(256), 0, s, A, lda, n, c, j, jb, keys, ipiv,
-                         info);
-      const int64_t rows = n - c - 1;
-      if (rows > 0)
-        hipLaunchKernelGGL(panel_update_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
-                           A, lda, n, c, j, jb, keys);
+    const int64_t rows = n - j;
+    int64_t R = (rows + gmax - 1) / gmax;
+    if (R < 8) R = 8;
+    const int64_t G = (rows + R - 1) / R;
+    const bool lds = R * jb <= kPanelLds;
+    if (G > (lds ? per_cu_lds : per_cu_glb) * (int64_t)cus) {
+      rc = -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+      break;
+    }
+    int jb_i = (int)jb, R_i = (int)R;
+    void* args[] = {&A, &lda, &n, &j, &jb_i, &R_i, &slot, &crow, &rowc, &ipiv, &info};
+    const void* fn = lds ? reinterpret_cast<const void*>(&lu_panel_kernel<true>)
+                         : reinterpret_cast<const void*>(&lu_panel_kernel<false>);
+    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, s);
+    if (e != hipSuccess) {
+      rc = -1000 - (int)e;
+      break;
     }
     if (n - jb > 0)
       hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((n - jb + 255) / 256)), dim3(256), 0, s, A, lda,
@@ -344,15 +573,14 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
     if (rest > 0) {
       hipLaunchKernelGGL(trsm_lu_kernel, dim3((unsigned)((rest + 3) / 4)), dim3(256), 0, s, A, lda, n, j,
                          jb);
-      const int rc = launch_gemm_ex(s, 0, 0, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
-                                    A + j * lda + j + jb, lda, kOne, A + (j + jb) * lda + j + jb, lda,
-                                    false, nullptr);
-      if (rc != 0) return rc;
+      rc = launch_gemm_ex(s, 0, 0, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
+                          A + j * lda + j + jb, lda, kOne, A + (j + jb) * lda + j + jb, lda, false,
+                          nullptr);
     }
-    const int rc = launch_status();
-    if (rc != 0) return rc;
+    if (rc == 0) rc = launch_status();
   }
-  e = hipFreeAsync(keys, s);
+  e = hipFreeAsync(ws, s);
+  if (rc != 0) return rc;
   if (e != hipSuccess) return -1000 - (int)e;
   return launch_status();
 }

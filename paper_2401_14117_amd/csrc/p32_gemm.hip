@@ -180,7 +180,12 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
 // LOWER: only the lower triangle (row >= column) of C is computed and written
 // (the trailing update of a Cholesky factorisation).  skip: when non-null and
 // nonzero on entry, the kernel does nothing (a failed factorisation step).
-template <bool TA, bool TB, bool LOWER>
+// CHAIN: instead of Rgemm, each C_ij gets the chain of fused updates
+// C_ij = rnd(C_ij - rnd(a_ip * b_pj)) for p = 0, 1, ..., k-1 in order (the
+// unblocked factorisations' rank-1 updates, applied k columns at a time); it
+// runs as the same k loop with the accumulators starting at C and op(A)
+// negated (rnd(-x) = -rnd(x) exactly), and alpha and beta are not used.
+template <bool TA, bool TB, bool LOWER, bool CHAIN>
 __global__ void __launch_bounds__(NT, P32_GEMM_MIN_WAVES)
 gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
             const uint32_t* __restrict__ B, int64_t ldb, uint32_t* __restrict__ C, int64_t ldc,
@@ -215,10 +220,22 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
   lut[tid] = round_params(tid - 128);   // NT == 256 entries
 
   win acc[TM][TN];
+  uint32_t cnar = 0;            // CHAIN: bit i*TN+j set when C_ij starts as NaR
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) { acc[i][j].h = 0; acc[i][j].e = kEZeroB; }
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j].h = 0;
+      acc[i][j].e = kEZeroB;
+      if (CHAIN) {
+        const int64_t gi = i0 + ty * TM + i, gj = j0 + tx * TN + j;
+        if (gi < m && gj < n && !(LOWER && gj > gi)) {
+          const uint32_t c = C[gi * ldc + gj];
+          if (c == kNaR) cnar |= 1u << (i * TN + j);
+          else acc[i][j] = bias(win_of(c));
+        }
+      }
+    }
 
   for (int64_t p0 = 0; p0 < k; p0 += BK) {
     int my_ok = 1;
@@ -236,7 +253,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
       if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
       const dec d = decode(v);
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
-      As[pp][ii] = make_int2(d.s * 8, d.sc + EB + 4);
+      As[pp][ii] = make_int2((CHAIN ? -d.s : d.s) * 8, d.sc + EB + 4);
     }
 #pragma unroll
     for (int l = 0; l < (BN * BK) / NT; ++l) {
@@ -271,7 +288,7 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
     const bool safe = __syncthreads_and(my_ok);
 
     int p = 0;
-    if (p0 == 0) {        // first step: accumulators are zero, use the checked path
+    if (p0 == 0) {        // first step: accumulators not yet tested, use the checked path
       k_step<true>(acc, As[0], Bs[0], lut, tx, ty);
       p = 1;
     }
@@ -294,6 +311,10 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
       const int64_t gj = j0 + tx * TN + j;
       if (gj >= n || (LOWER && gj > gi)) continue;
       const int nar = rowNaR[ty * TM + i] | colNaR[tx * TN + j];
+      if (CHAIN) {
+        C[gi * ldc + gj] = nar || ((cnar >> (i * TN + j)) & 1u) ? kNaR : encode_exact(unbias(acc[i][j]));
+        continue;
+      }
       const uint32_t c = beta ? C[gi * ldc + gj] : 0u;
       C[gi * ldc + gj] = gemm_epilogue(unbias(acc[i][j]), nar, alpha, beta, c);
     }
@@ -331,8 +352,8 @@ int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t 
   const dim3 grid((unsigned)tiles);
   const dim3 block(NT);
 #define P32_LAUNCH(TA_, TB_, LO_) \
-  hipLaunchKernelGGL((gemm_kernel<TA_, TB_, LO_>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, \
-                     ldc, alpha, beta, skip)
+  hipLaunchKernelGGL((gemm_kernel<TA_, TB_, LO_, false>), grid, block, 0, s, m, n, k, A, lda, B, ldb, \
+                     C, ldc, alpha, beta, skip)
   if (lower) {
     if (!ta && tb) P32_LAUNCH(false, true, true);
     else return -1;                                   // only the Cholesky form is needed
@@ -340,6 +361,25 @@ int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t 
   else if (!ta && tb) P32_LAUNCH(false, true, false);
   else if (ta && !tb) P32_LAUNCH(true, false, false);
   else P32_LAUNCH(true, true, false);
+#undef P32_LAUNCH
+  return launch_status();
+}
+
+int launch_fms_chain(hipStream_t s, int tb, int64_t m, int64_t n, int64_t k, const uint32_t* A,
+                     int64_t lda, const uint32_t* B, int64_t ldb, uint32_t* C, int64_t ldc, bool lower,
+                     const int32_t* skip) {
+  if (m == 0 || n == 0 || k == 0) return 0;
+  const int64_t tiles = ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
+  if (tiles * NT >= ((int64_t)1 << 32)) return -4;
+  const dim3 grid((unsigned)tiles);
+  const dim3 block(NT);
+#define P32_LAUNCH(TB_, LO_) \
+  hipLaunchKernelGGL((gemm_kernel<false, TB_, LO_, true>), grid, block, 0, s, m, n, k, A, lda, B, ldb, \
+                     C, ldc, 0u, 0u, skip)
+  if (tb && lower) P32_LAUNCH(true, true);
+  else if (tb) P32_LAUNCH(true, false);
+  else if (!lower) P32_LAUNCH(false, false);
+  else return -1;
 #undef P32_LAUNCH
   return launch_status();
 }

@@ -305,15 +305,25 @@ constexpr int kPotf2Threads = 1024;
 __device__ __forceinline__ int tri_off(int i) { return i * (i + 1) / 2; }
 
 __global__ void __launch_bounds__(kPotf2Threads)
-potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* __restrict__ info) {
+potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* __restrict__ info,
+             const uint32_t* __restrict__ saved) {
   __shared__ uint32_t D[kTri];
   __shared__ uint32_t col[kMaxNB];
   __shared__ int stop;
-  if (*info != 0) return;
   const int t = threadIdx.x;
   uint32_t* G = A + j * lda + j;
-  for (int i = t >> 6; i < jb; i += kPotf2Threads / 64)
-    for (int q = t & 63; q <= i; q += 64) D[tri_off(i) + q] = G[i * lda + q];
+  if (saved == nullptr) {
+    if (*info != 0) return;
+    for (int i = t >> 6; i < jb; i += kPotf2Threads / 64)
+      for (int q = t & 63; q <= i; q += 64) D[tri_off(i) + q] = G[i * lda + q];
+  } else {
+    // redo the whole block from its saved lower triangle (kept with row
+    // stride kMaxNB) when a sub-block of it failed; see launch_potrf
+    const int32_t f = *info;
+    if (f < j + 1 || f > j + jb) return;
+    for (int i = t >> 6; i < jb; i += kPotf2Threads / 64)
+      for (int q = t & 63; q <= i; q += 64) D[tri_off(i) + q] = saved[i * kMaxNB + q];
+  }
   __syncthreads();
   int c = 0;
   for (; c < jb; ++c) {
@@ -352,12 +362,12 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
 // Column by column: x_c = A[r][c] / L[c][c] is final once the updates from
 // columns < c are in, then columns c' > c get A[r][c'] - rnd(x_c * L[c'][c]).
 __global__ void __launch_bounds__(256)
-trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb,
-                 const int32_t* __restrict__ info) {
+trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t r_end, int64_t j,
+                 int64_t jb, const int32_t* __restrict__ info) {
   if (*info != 0) return;
   const int lane = threadIdx.x & 63;
-  const int64_t r = j + jb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= n) return;
+  const int64_t r = r_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= r_end) return;
   uint32_t* row = A + r * lda + j;
   const uint32_t* L = A + j * lda + j;
   uint32_t v[4];
@@ -595,23 +605,74 @@ int launch_getrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* LU, int
   return trsv(s, LU, lda, n, B, ldb, nrhs, 1);
 }
 
+// lower triangle of the jb x jb block at A[j][j] -> dst (row stride kMaxNB)
+__global__ void save_lower_kernel(const uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb,
+                                  uint32_t* __restrict__ dst, const int32_t* __restrict__ info) {
+  if (*info != 0) return;
+  const int i = blockIdx.x;
+  for (int q = threadIdx.x; q <= i && q < jb; q += blockDim.x)
+    dst[i * kMaxNB + q] = A[(j + i) * lda + j + q];
+}
+
+constexpr int64_t kCholSub = 32;     // columns per sub-block of a diagonal block
+
+// Rpotrf.  Each diagonal block [j, j+jb) is factored kCholSub columns at a
+// time: the sub-block's own columns by potf2_kernel, the block's rows below
+// it by trsm_chol_kernel, and the rest of the block's lower triangle by one
+// fused-update chain over the sub-block's columns.  Every element receives
+// exactly the updates, divisions and square root of the unblocked order, in
+// the same sequence.  If a diagonal fails, the partial state of the
+// sub-blocked schedule differs from the unblocked one, so the block is
+// restored from a copy taken before it started and refactored unblocked,
+// which stops at the same column with the state the unblocked order leaves.
+// L21 = A21 L11^-T is then computed with the same sub-blocks (solve against
+// the sub-block's triangle, then a chain update of the later columns).
 int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
-  for (int64_t j = 0; j < n; j += nb) {
+  if (n == 0) return launch_status();
+  uint32_t* saved = nullptr;
+  hipError_t e = hipMallocAsync((void**)&saved, (size_t)kMaxNB * kMaxNB * sizeof(uint32_t), s);
+  if (e != hipSuccess) return -1000 - (int)e;
+  int rc = launch_status();
+  for (int64_t j = 0; j < n && rc == 0; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;
-    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(1024), 0, s, A, lda, j, jb, info);
-    const int64_t rest = n - j - jb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((rest + 3) / 4)), dim3(256), 0, s, A, lda, n,
-                         j, jb, info);
-      const int rc = launch_gemm_ex(s, 0, 1, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
-                                    A + (j + jb) * lda + j, lda, kOne, A + (j + jb) * lda + j + jb, lda,
-                                    true, info);
-      if (rc != 0) return rc;
+    hipLaunchKernelGGL(save_lower_kernel, dim3((unsigned)jb), dim3(256), 0, s, A, lda, j, (int)jb, saved,
+                       info);
+    for (int64_t c0 = j; c0 < j + jb && rc == 0; c0 += kCholSub) {
+      const int64_t sb = kCholSub < j + jb - c0 ? kCholSub : j + jb - c0;
+      hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kPotf2Threads), 0, s, A, lda, c0, (int)sb, info,
+                         (const uint32_t*)nullptr);
+      const int64_t r1 = c0 + sb, rin = j + jb - r1;
+      if (rin > 0) {
+        hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((rin + 3) / 4)), dim3(256), 0, s, A, lda, r1,
+                           j + jb, c0, sb, info);
+        rc = launch_fms_chain(s, 1, rin, rin, sb, A + r1 * lda + c0, lda, A + r1 * lda + c0, lda,
+                              A + r1 * lda + r1, lda, true, info);
+      }
     }
-    const int rc = launch_status();
-    if (rc != 0) return rc;
+    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kPotf2Threads), 0, s, A, lda, j, (int)jb, info,
+                       (const uint32_t*)saved);
+    const int64_t rest = n - j - jb;
+    if (rest > 0 && rc == 0) {
+      const int64_t r0 = j + jb;
+      for (int64_t c0 = j; c0 < j + jb && rc == 0; c0 += kCholSub) {
+        const int64_t sb = kCholSub < j + jb - c0 ? kCholSub : j + jb - c0;
+        hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((rest + 3) / 4)), dim3(256), 0, s, A, lda, r0,
+                           n, c0, sb, info);
+        const int64_t later = j + jb - (c0 + sb);
+        if (later > 0)
+          rc = launch_fms_chain(s, 1, rest, later, sb, A + r0 * lda + c0, lda, A + (c0 + sb) * lda + c0,
+                                lda, A + r0 * lda + c0 + sb, lda, false, info);
+      }
+      if (rc == 0)
+        rc = launch_gemm_ex(s, 0, 1, rest, rest, jb, kMinusOne, A + r0 * lda + j, lda, A + r0 * lda + j,
+                            lda, kOne, A + r0 * lda + r0, lda, true, info);
+    }
+    if (rc == 0) rc = launch_status();
   }
+  e = hipFreeAsync(saved, s);
+  if (rc != 0) return rc;
+  if (e != hipSuccess) return -1000 - (int)e;
   return launch_status();
 }
 

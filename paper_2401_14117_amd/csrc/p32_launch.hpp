@@ -18,6 +18,11 @@ int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, 
 int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
                    const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
                    uint32_t* C, int64_t ldc, bool lower, const int32_t* skip);
+// C_ij = rnd(C_ij - rnd(A_ip * op(B)_pj)) for p = 0 .. k-1 in order (A not
+// transposed; op(B) = B or B^T by tb; lower: only row >= column of C)
+int launch_fms_chain(hipStream_t s, int tb, int64_t m, int64_t n, int64_t k, const uint32_t* A,
+                     int64_t lda, const uint32_t* B, int64_t ldb, uint32_t* C, int64_t ldc, bool lower,
+                     const int32_t* skip);
 int launch_from_f64(hipStream_t s, int64_t n, const double* x, uint32_t* out);
 int launch_to_f64(hipStream_t s, int64_t n, const uint32_t* p, double* out);
 int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, const uint32_t* b,

@@ -16,7 +16,7 @@ import re
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL = "_ZN3p3211gemm_kernelILb0ELb0ELb0EEEvlllPKjlS2_lPjljjPKi"
+KERNEL = "_ZN3p3211gemm_kernelILb0ELb0ELb0ELb0EEEvlllPKjlS2_lPjljjPKi"
 MADDS_PER_STEP = 8    # TM * TN of the kernel
 
 

@@ -76,7 +76,66 @@ def make_case(name: str):
     if name.startswith("uniform_n"):
         n = int(name[len("uniform_n"):])
         return W.gemm_uniform(n, n, n, seed=1)
+    if name.startswith("normal_sigma"):           # normal_sigma<S>_n<N>
+        sig, n = name[len("normal_sigma"):].split("_n")
+        return W.gemm_normal(int(n), float(sig))
     raise SystemExit(f"unknown workload {name}")
+
+
+STREAM_PROCESSORS = 256 * 64      # MI355X: 256 CUs x 64 lanes
+EW_OPS = {"add": 0, "mul": 2, "div": 3, "sqrt": 4}
+
+
+def run_elementwise_bench(name: str, args, dev) -> dict:
+    """ew_<op>_<range>: the paper's elementwise kernel study (Section 4.2,
+    Table 2) -- n operations on arrays p, q drawn from one magnitude range.
+    One step = one posit32_elementwise launch over the whole arrays."""
+    import torch
+    from paper_2401_14117_amd import posit32
+    from paper_2401_14117_amd import workloads as W
+    _, op_name, rng_name = name.split("_")
+    op = EW_OPS[op_name]
+    n = args.ew_n
+    p, q = W.elementwise_range(n, rng_name)
+    P = posit32.from_f64(torch.from_numpy(p).to(dev))
+    Q = posit32.from_f64(torch.from_numpy(q).to(dev))
+    out = torch.empty_like(P)
+    stream = torch.cuda.current_stream()
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        posit32.elementwise(op, P, None if op == 4 else Q, out=out)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    nbytes = n * (8 if op == 4 else 12)
+    return {
+        "metric": f"Posit32 elementwise {op_name} Gop/s ({rng_name})",
+        "value": round(n / (kms * 1e-3) / 1e9, 2),
+        "unit": "Gop/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "posit32 (int32 VALU)",
+        "data": "synthetic",
+        "config": {"workload": name, "n": n, "range": list(W.RANGES[rng_name]),
+                   "kernel_ms": round(kms, 4),
+                   "ns_per_op_per_stream_processor": round(kms * 1e6 * STREAM_PROCESSORS / n, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (kms * 1e-3) / 1e9, 1),
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(nbytes / (kms * 1e-3) / 1e9 / 8000.0, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
 
 
 def run_solve_bench(name: str, args, dev) -> dict:
@@ -204,7 +263,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="square_n8192",
-                    help="square_nN | trailing_jJ | uniform_nN (Rgemm), getrf_nN | potrf_nN (factor+solve)")
+                    help="square_nN | trailing_jJ | uniform_nN | normal_sigmaS_nN (Rgemm), "
+                         "getrf_nN | potrf_nN (factor+solve), ew_OP_IR (elementwise, "
+                         "OP in add/mul/div/sqrt, R in 0..4)")
+    ap.add_argument("--trans", default="nn", choices=["nn", "nt", "tn", "tt"],
+                    help="Rgemm transposes op(A), op(B) (square workloads reuse the buffers)")
+    ap.add_argument("--ew-n", type=int, default=1 << 26, help="elements of the elementwise workloads")
     ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
@@ -235,8 +299,19 @@ def main() -> int:
     if args.workload.startswith(("getrf_n", "potrf_n")):
         print(json.dumps(run_solve_bench(args.workload, args, dev)))
         return 0
+    if args.workload == "ew_all":                 # the whole Table 2 grid, one line each
+        for r in ("I0", "I1", "I2", "I3", "I4"):
+            for op in EW_OPS:
+                print(json.dumps(run_elementwise_bench(f"ew_{op}_{r}", args, dev)), flush=True)
+        return 0
+    if args.workload.startswith("ew_"):
+        print(json.dumps(run_elementwise_bench(args.workload, args, dev)))
+        return 0
 
     case = make_case(args.workload)
+    ta, tb = args.trans[0] == "t", args.trans[1] == "t"
+    if (ta or tb) and not (case.m == case.n == case.k):
+        raise SystemExit("--trans needs a square workload")
     t0 = time.perf_counter()
     A = to_device_patterns(case.A, dev)
     B = to_device_patterns(case.B, dev)
@@ -254,7 +329,7 @@ def main() -> int:
         C.copy_(C0)
         if ev0 is not None:
             ev0.record(stream)
-        posit32.gemm(A, B, C, alpha, beta)
+        posit32.gemm(A, B, C, alpha, beta, transa=ta, transb=tb)
         if ev1 is not None:
             ev1.record(stream)
 
@@ -280,7 +355,7 @@ def main() -> int:
 
     valu = load_valu_per_madd()
     roof = {"bound": "alu", "achieved": None, "peak": round(PEAK_INT_TOPS, 2),
-            "unit": "Tlane-op/s", "frac": None, "traffic": load_traffic(args.workload),
+            "unit": "Tlane-op/s", "frac": None, "traffic": load_traffic(args.workload) if args.trans == "nn" else None,
             "kernel_ms": round(kavg, 3), "valu_per_madd": valu,
             "kernel_gpops": round(2.0 * madds / (kavg * 1e-3) / 1e9, 2)}
     if valu is not None:
@@ -289,7 +364,7 @@ def main() -> int:
         roof["frac"] = round(achieved / PEAK_INT_TOPS, 4)
 
     cpu = None
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and args.trans == "nn":
         cpu = run_cpu_baseline(case, args.cpu_budget)
 
     out = {
@@ -305,10 +380,11 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "posit32 (int32 VALU)",
         "data": "synthetic",
-        "config": {"workload": case.name, "m": m, "n": n, "k": k,
+        "config": {"workload": case.name, "m": m, "n": n, "k": k, "trans": args.trans,
                    "alpha": case.alpha, "beta": case.beta,
                    "inputs": "uniform[-1,1]*2^s, s in [-12,12], NaR/0 sprinkle 1e-6"
-                   if "square" in case.name or "trailing" in case.name else "uniform[-1,1]",
+                   if "square" in case.name or "trailing" in case.name else
+                   ("normal(0, sigma)" if "normal" in case.name else "uniform[-1,1]"),
                    "setup_s": round(setup_s, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,

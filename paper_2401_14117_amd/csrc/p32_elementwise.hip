@@ -1,6 +1,8 @@
 // p32_elementwise.hip -- conversions and elementwise Posit(32,2) arithmetic
-// (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2), on the general exact
-// routines of p32_device.hpp.  Grid-stride loops; every element independent.
+// (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2): add and multiply take
+// the window-form fast path with the exact routines as fallback, divide and
+// square root the exact routines.  Grid-stride loops; every element
+// independent.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -63,11 +65,11 @@ __global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict
       case 0:
       case 1: {
         const uint32_t yy = op == 1 ? 0u - y : y;
-        r = (xn || yn) ? kNaR : add_general(win_of(x), win_of(yy));
+        r = (xn || yn) ? kNaR : encode_win(add_win(win_of(x), win_of(yy)));
         break;
       }
       case 2:
-        r = (xn || yn) ? kNaR : mul_general(decode(x), decode(y));
+        r = (xn || yn) ? kNaR : encode_win(mul_win(decode(x), decode(y)));
         break;
       case 3:
         r = div_general(decode(x), decode(y), xn, yn);

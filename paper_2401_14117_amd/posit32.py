@@ -131,7 +131,8 @@ def to_f64(p: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
-def elementwise(op: int, a: torch.Tensor, b: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+def elementwise(op: int, a: torch.Tensor, b: torch.Tensor | None = None, stream=None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
     _is_i32_cuda(a)
     a = a.contiguous()
     if b is not None:
@@ -139,7 +140,12 @@ def elementwise(op: int, a: torch.Tensor, b: torch.Tensor | None = None, stream=
         b = b.contiguous()
         if b.shape != a.shape:
             raise ValueError("shape mismatch")
-    out = torch.empty_like(a)
+    if out is None:
+        out = torch.empty_like(a)
+    else:
+        _is_i32_cuda(out)
+        if out.shape != a.shape or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of a's shape")
     _check(lib().posit32_elementwise(_stream(stream), op, a.numel(), _ptr(a), _ptr(b), _ptr(out)),
            "posit32_elementwise")
     return out

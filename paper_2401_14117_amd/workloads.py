@@ -17,7 +17,13 @@ listed, row-major):
   alpha = beta = 1; the trailing-update shapes m = n = 8192 - 256 j, k = 256
   use seed 3000 + j with alpha = -1, beta = 1.
 * ``gemm_normal``: normal(0, sigma) entries, the paper's GEMM inputs
-  (Section 4.3); used for the magnitude sweep.
+  (Section 4.3); used for the magnitude sweep, sigma in {1e-2, 1, 1e2, 1e4,
+  1e6}, seed 77, alpha = beta = 1.
+* ``elementwise_range``: the operand arrays p and q of the elementwise
+  microbenchmark, each ``uniform(a, b)`` over one of the paper's magnitude
+  ranges I0..I4 (Section 4.2, Table 2), seed 8000 + range index.  Values
+  beyond maxpos or below minpos saturate on conversion, as they would in any
+  posit program fed these inputs.
 """
 from __future__ import annotations
 
@@ -129,3 +135,22 @@ def chol_case(n: int, nrhs: int = 1) -> SolveCase:
     A = Bm @ Bm.T / n + np.eye(n)
     b = A @ np.ones((n, nrhs))
     return SolveCase(f"potrf_n{n}", n, A, b, "chol")
+
+
+# magnitude ranges [a, b) of the paper's elementwise kernel study (Table 2)
+RANGES = {
+    "I0": (1.0, 2.0),
+    "I1": (1e-38, 1e-30),
+    "I2": (1e30, 1e38),
+    "I3": (1e-15, 1e-14),
+    "I4": (1e14, 1e15),
+}
+
+
+def elementwise_range(n: int, rng_name: str) -> tuple[np.ndarray, np.ndarray]:
+    """p, q ~ uniform[a, b) for range rng_name (seed 8000 + its index)."""
+    a, b = RANGES[rng_name]
+    rng = np.random.default_rng(8000 + int(rng_name[1:]))
+    p = rng.uniform(a, b, n)
+    q = rng.uniform(a, b, n)
+    return p, q

@@ -34,7 +34,7 @@ PKG = os.path.join(ROOT, "paper_2401_14117_amd")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("p32_device.hpp", "p32_gemm.hip"):
+    for f in ("p32_device.hpp", "p32_gemm_tile.hpp", "p32_gemm.hip"):
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -207,6 +207,150 @@ def run_solve_bench(name: str, args, dev) -> dict:
     }
 
 
+def run_batch_bench(name: str, args, dev) -> dict:
+    """batch_lu / batch_chol: the variable-size batched workload -- count
+    systems (n log-uniform in [16, 512], nrhs in [1, 16]) factored and solved
+    by one persistent launch (posit32_gesv_vbatched / posit32_posv_vbatched).
+    One step = the whole batch, inputs resident in HBM (restored between steps
+    outside the timed region).  Beside it: the same library's single-matrix
+    calls, one system at a time, on a random sample of the batch (their
+    results are also compared with the batched ones bit for bit)."""
+    import torch
+    from paper_2401_14117_amd import posit32
+    from paper_2401_14117_amd import workloads as W
+    kind = "lu" if name == "batch_lu" else "chol"
+    n, nrhs = W.batch_sizes(args.batch_count)
+    count = len(n)
+    t0 = time.perf_counter()
+    offA = np.concatenate([[0], np.cumsum(n * n)])
+    offB = np.concatenate([[0], np.cumsum(n * nrhs)])
+    A0 = torch.empty(int(offA[-1]), dtype=torch.int32, device=dev)
+    B0 = torch.empty(int(offB[-1]), dtype=torch.int32, device=dev)
+    pend_a, pend_b, first = [], [], 0
+    flushed = 0
+
+    def flush(upto):
+        nonlocal pend_a, pend_b, first
+        if not pend_a:
+            return
+        a = torch.from_numpy(np.concatenate(pend_a)).to(dev)
+        b = torch.from_numpy(np.concatenate(pend_b)).to(dev)
+        posit32.from_f64(a, out=A0[int(offA[first]):int(offA[upto])])
+        posit32.from_f64(b, out=B0[int(offB[first]):int(offB[upto])])
+        pend_a, pend_b, first = [], [], upto
+
+    for i, A, B in W.batch_matrices(kind, n, nrhs):
+        pend_a.append(A.ravel())
+        pend_b.append(B.ravel())
+        flushed += A.size
+        if flushed >= (32 << 20):
+            flush(i + 1)
+            flushed = 0
+    flush(count)
+    A = A0.clone()
+    B = B0.clone()
+    order = np.argsort(-n, kind="stable")          # decreasing n balances the workgroups
+    As = [A[int(offA[i]):int(offA[i + 1])].view(int(n[i]), int(n[i])) for i in order]
+    Bs = [B[int(offB[i]):int(offB[i + 1])].view(int(n[i]), int(nrhs[i])) for i in order]
+    vb = posit32.VBatch(As, Bs, lu=(kind == "lu"))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+
+    def step(ev0=None, ev1=None):
+        A.copy_(A0)
+        B.copy_(B0)
+        if ev0 is not None:
+            ev0.record(stream)
+        if kind == "lu":
+            vb.gesv(args.nb)
+        else:
+            vb.posv(args.nb)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for e0, e1 in evs:
+        step(e0, e1)
+    torch.cuda.synchronize()
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    info = vb.info.cpu().numpy()
+    fac = (2.0 if kind == "lu" else 1.0) / 3.0
+    pops = float(np.sum(fac * n.astype(np.float64) ** 3))
+
+    # one system at a time through the single-matrix entry points, on a sample
+    rs = np.random.default_rng(6001)
+    sample = np.sort(rs.choice(count, size=min(args.single_count, count), replace=False))
+    A.copy_(A0)
+    B.copy_(B0)
+    torch.cuda.synchronize()
+    views = [(A[int(offA[i]):int(offA[i + 1])].view(int(n[i]), int(n[i])),
+              B[int(offB[i]):int(offB[i + 1])].view(int(n[i]), int(nrhs[i]))) for i in sample]
+    t1 = time.perf_counter()
+    for Ai, Bi in views:
+        if kind == "lu":
+            _, ipiv, _ = posit32.getrf(Ai, args.nb)
+            posit32.getrs(Ai, ipiv, Bi)
+        else:
+            posit32.potrf(Ai, args.nb)
+            posit32.potrs(Ai, Bi)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t1
+    single = {"sample": len(sample), "seconds": round(single_s, 3),
+              "solves_per_s": round(len(sample) / single_s, 1),
+              "sample_pops_share": round(float(np.sum(fac * n[sample].astype(np.float64) ** 3)) / pops, 5)}
+    # bit-compare the sampled single-matrix results with the batched ones
+    A_single = torch.cat([A[int(offA[i]):int(offA[i + 1])] for i in sample])
+    B_single = torch.cat([B[int(offB[i]):int(offB[i + 1])] for i in sample])
+    A.copy_(A0)
+    B.copy_(B0)
+    vb.gesv(args.nb) if kind == "lu" else vb.posv(args.nb)
+    torch.cuda.synchronize()
+    A_b = torch.cat([A[int(offA[i]):int(offA[i + 1])] for i in sample])
+    B_b = torch.cat([B[int(offB[i]):int(offB[i + 1])] for i in sample])
+    single["bit_identical_to_batched"] = bool(torch.equal(A_single, A_b) and torch.equal(B_single, B_b))
+    # expected ratio if the single calls ran the whole batch: scale by work share
+    single["whole_batch_s_est"] = round(single_s / max(single["sample_pops_share"], 1e-12), 2)
+
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle as O
+        done, tcpu = 0, time.perf_counter()
+        for i, Af, Bf in W.batch_matrices(kind, n, nrhs, start=0, stop=count):
+            Ap = O.vec_from_double(Af)
+            Bp = O.vec_from_double(Bf)
+            if kind == "lu":
+                LU, ipiv, _ = O.getrf(Ap, args.nb)
+                O.getrs(LU, ipiv, Bp)
+            else:
+                L, _ = O.potrf(Ap, args.nb)
+                O.potrs(L, Bp)
+            done += 1
+            if time.perf_counter() - tcpu > args.cpu_budget:
+                break
+        el = time.perf_counter() - tcpu
+        cpu = {"value": round(done / el, 3), "unit": "solves/s", "cores": O.num_threads(),
+               "kind": "oracle", "sample": f"first {done} systems of the batch (in generation order)"}
+
+    return {
+        "metric": f"Posit32 batched {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s",
+        "value": round(count / (kms * 1e-3), 1),
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(kms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "posit32 (int32 VALU)", "data": "synthetic",
+        "config": {"workload": name, "count": count, "n": "round(exp(U(ln 16, ln 512)))",
+                   "nrhs": "1..16", "nb": args.nb, "factor_gpops": round(pops / (kms * 1e-3) / 1e9, 1),
+                   "info_nonzero": int(np.count_nonzero(info)), "setup_s": round(setup_s, 1),
+                   "one_at_a_time": single},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+
+
 def to_device_patterns(mat, dev):
     """FP64 values -> Posit(32,2) patterns with the library's own conversion;
     the sprinkled special values are then set by index."""
@@ -264,11 +408,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="square_n8192",
                     help="square_nN | trailing_jJ | uniform_nN | normal_sigmaS_nN (Rgemm), "
-                         "getrf_nN | potrf_nN (factor+solve), ew_OP_IR (elementwise, "
-                         "OP in add/mul/div/sqrt, R in 0..4)")
+                         "getrf_nN | potrf_nN (factor+solve), batch_lu | batch_chol (batched "
+                         "factor+solve), ew_OP_IR | ew_all (elementwise, OP in add/mul/div/sqrt, "
+                         "R in 0..4)")
     ap.add_argument("--trans", default="nn", choices=["nn", "nt", "tn", "tt"],
                     help="Rgemm transposes op(A), op(B) (square workloads reuse the buffers)")
     ap.add_argument("--ew-n", type=int, default=1 << 26, help="elements of the elementwise workloads")
+    ap.add_argument("--batch-count", type=int, default=20000, help="systems of the batched workloads")
+    ap.add_argument("--single-count", type=int, default=300,
+                    help="sampled systems timed one at a time beside the batched workloads")
     ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
@@ -298,6 +446,9 @@ def main() -> int:
 
     if args.workload.startswith(("getrf_n", "potrf_n")):
         print(json.dumps(run_solve_bench(args.workload, args, dev)))
+        return 0
+    if args.workload in ("batch_lu", "batch_chol"):
+        print(json.dumps(run_batch_bench(args.workload, args, dev)))
         return 0
     if args.workload == "ew_all":                 # the whole Table 2 grid, one line each
         for r in ("I0", "I1", "I2", "I3", "I4"):

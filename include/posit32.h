@@ -158,6 +158,59 @@ int posit32_potrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
 int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
                   posit32_t* B, int64_t ldb);
 
+/*
+ * Variable-size batches of the factorisations and solves above: count
+ * independent systems in one persistent launch (many small systems, the
+ * sizes of the paper's LU and Cholesky study, Section 5, in large numbers).
+ * Matrix i is factored and solved exactly as the single-matrix call with the
+ * same nb would do it, bit for bit.
+ *
+ *   count        number of systems, >= 0.
+ *   max_n        host-side bound, 0 <= n[i] <= max_n <= 2^24 - 2 (a matrix
+ *                with a larger n[i] is rejected through its info[i]).
+ *   nb           block size, 1 <= nb <= 256.
+ *   n, nrhs      device int32[count]: order and right-hand sides of system i.
+ *   A (LU, L)    device array of count device pointers to row-major n[i] x
+ *                n[i] matrices; lda device int64[count], lda[i] >= max(1, n[i]).
+ *   ipiv         device array of count device pointers to int32[n[i]].
+ *   B            device array of count device pointers to row-major n[i] x
+ *                nrhs[i] matrices; ldb device int64[count], ldb[i] >=
+ *                max(1, nrhs[i]).
+ *   info         device int32[count], written for every system: 0, or (the
+ *                factorisations) the 1-based column of the first zero pivot /
+ *                failed diagonal as in the single-matrix calls, or a negative
+ *                code for an invalid system, which is then left untouched:
+ *                -1 n[i] outside [0, max_n], -2 null A[i] with n[i] > 0,
+ *                -3 bad lda[i], -4 null ipiv[i] (LU, n[i] > 0), -5 nrhs[i] < 0,
+ *                -6 null B[i] with n[i], nrhs[i] > 0, -7 bad ldb[i].
+ * posit32_gesv_vbatched / posit32_posv_vbatched factor and solve in the same
+ * launch; a system whose factorisation reports info > 0 is not solved.
+ * Workgroups take the systems round-robin (system i goes to workgroup
+ * i mod G), so a batch ordered by decreasing n balances best.  The calls
+ * allocate nothing and launch one kernel (they can be captured in a graph).
+ * Systems must not share memory.  Errors: -2 count < 0, -3 bad max_n,
+ * -4 bad nb, -5 a null array argument with count > 0.
+ */
+int posit32_getrf_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                           posit32_t* const* A, const int64_t* lda, int32_t* const* ipiv,
+                           int32_t* info);
+int posit32_getrs_vbatched(void* stream, int32_t count, int32_t max_n, const int32_t* n,
+                           const int32_t* nrhs, posit32_t* const* LU, const int64_t* lda,
+                           int32_t* const* ipiv, posit32_t* const* B, const int64_t* ldb,
+                           int32_t* info);
+int posit32_gesv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                          const int32_t* nrhs, posit32_t* const* A, const int64_t* lda,
+                          int32_t* const* ipiv, posit32_t* const* B, const int64_t* ldb,
+                          int32_t* info);
+int posit32_potrf_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                           posit32_t* const* A, const int64_t* lda, int32_t* info);
+int posit32_potrs_vbatched(void* stream, int32_t count, int32_t max_n, const int32_t* n,
+                           const int32_t* nrhs, posit32_t* const* L, const int64_t* lda,
+                           posit32_t* const* B, const int64_t* ldb, int32_t* info);
+int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                          const int32_t* nrhs, posit32_t* const* A, const int64_t* lda,
+                          posit32_t* const* B, const int64_t* ldb, int32_t* info);
+
 #ifdef __cplusplus
 }
 #endif

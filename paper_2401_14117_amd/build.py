@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposit32.so")
-SOURCES = ["p32_gemm.hip", "p32_elementwise.hip", "p32_lapack.hip", "p32_api.cpp"]
+SOURCES = ["p32_gemm.hip", "p32_elementwise.hip", "p32_lapack.hip", "p32_batched.hip", "p32_api.cpp"]
 ARCH = "gfx950"
 
 

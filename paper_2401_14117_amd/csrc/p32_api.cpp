@@ -108,4 +108,78 @@ int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int
   return p32::launch_potrs((hipStream_t)stream, n, nrhs, L, lda, B, ldb);
 }
 
+// ---- variable-size batches ---------------------------------------------------
+
+static int vb_common(int32_t count, int32_t max_n, const int32_t* n, posit32_t* const* A,
+                     const int64_t* lda, int32_t* info) {
+  if (count < 0) return -2;
+  if (max_n < 0 || max_n > 0xFFFFFE) return -3;
+  if (count > 0 && (n == nullptr || A == nullptr || lda == nullptr || info == nullptr)) return -5;
+  return 0;
+}
+
+int posit32_getrf_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                           posit32_t* const* A, const int64_t* lda, int32_t* const* ipiv,
+                           int32_t* info) {
+  const int rc = vb_common(count, max_n, n, A, lda, info);
+  if (rc) return rc;
+  if (nb < 1 || nb > 256) return -4;
+  if (count > 0 && ipiv == nullptr) return -5;
+  return p32::launch_vbatched((hipStream_t)stream, 0, true, false, count, max_n, nb, n, A, lda, ipiv,
+                              nullptr, nullptr, nullptr, info);
+}
+
+int posit32_getrs_vbatched(void* stream, int32_t count, int32_t max_n, const int32_t* n,
+                           const int32_t* nrhs, posit32_t* const* LU, const int64_t* lda,
+                           int32_t* const* ipiv, posit32_t* const* B, const int64_t* ldb,
+                           int32_t* info) {
+  const int rc = vb_common(count, max_n, n, LU, lda, info);
+  if (rc) return rc;
+  if (count > 0 && (nrhs == nullptr || ipiv == nullptr || B == nullptr || ldb == nullptr)) return -5;
+  return p32::launch_vbatched((hipStream_t)stream, 0, false, true, count, max_n, 1, n, LU, lda, ipiv,
+                              nrhs, B, ldb, info);
+}
+
+int posit32_gesv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                          const int32_t* nrhs, posit32_t* const* A, const int64_t* lda,
+                          int32_t* const* ipiv, posit32_t* const* B, const int64_t* ldb,
+                          int32_t* info) {
+  const int rc = vb_common(count, max_n, n, A, lda, info);
+  if (rc) return rc;
+  if (nb < 1 || nb > 256) return -4;
+  if (count > 0 && (nrhs == nullptr || ipiv == nullptr || B == nullptr || ldb == nullptr)) return -5;
+  return p32::launch_vbatched((hipStream_t)stream, 0, true, true, count, max_n, nb, n, A, lda, ipiv,
+                              nrhs, B, ldb, info);
+}
+
+int posit32_potrf_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                           posit32_t* const* A, const int64_t* lda, int32_t* info) {
+  const int rc = vb_common(count, max_n, n, A, lda, info);
+  if (rc) return rc;
+  if (nb < 1 || nb > 256) return -4;
+  return p32::launch_vbatched((hipStream_t)stream, 1, true, false, count, max_n, nb, n, A, lda, nullptr,
+                              nullptr, nullptr, nullptr, info);
+}
+
+int posit32_potrs_vbatched(void* stream, int32_t count, int32_t max_n, const int32_t* n,
+                           const int32_t* nrhs, posit32_t* const* L, const int64_t* lda,
+                           posit32_t* const* B, const int64_t* ldb, int32_t* info) {
+  const int rc = vb_common(count, max_n, n, L, lda, info);
+  if (rc) return rc;
+  if (count > 0 && (nrhs == nullptr || B == nullptr || ldb == nullptr)) return -5;
+  return p32::launch_vbatched((hipStream_t)stream, 1, false, true, count, max_n, 1, n, L, lda, nullptr,
+                              nrhs, B, ldb, info);
+}
+
+int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
+                          const int32_t* nrhs, posit32_t* const* A, const int64_t* lda,
+                          posit32_t* const* B, const int64_t* ldb, int32_t* info) {
+  const int rc = vb_common(count, max_n, n, A, lda, info);
+  if (rc) return rc;
+  if (nb < 1 || nb > 256) return -4;
+  if (count > 0 && (nrhs == nullptr || B == nullptr || ldb == nullptr)) return -5;
+  return p32::launch_vbatched((hipStream_t)stream, 1, true, true, count, max_n, nb, n, A, lda, nullptr,
+                              nrhs, B, ldb, info);
+}
+
 }  // extern "C"

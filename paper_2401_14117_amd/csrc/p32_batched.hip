@@ -1,0 +1,480 @@
+// p32_batched.hip -- variable-size batched Posit(32,2) LU and Cholesky
+// factorisations and solves: many small independent systems (the sizes of the
+// paper's LU and Cholesky study, Section 5, in large numbers) in one
+// persistent launch.
+//
+// One workgroup of 256 threads owns one matrix at a time and runs its whole
+// factorisation (and solve) without leaving the kernel: workgroup g takes the
+// matrices g, g + G, g + 2G, ... (G = number of workgroups), so a batch sorted
+// by decreasing size keeps the workgroups evenly loaded, and the launch needs
+// no counter, workspace or memset (it can be captured in a graph as is).
+//
+// Every matrix is processed in the schedule of the single-matrix routines
+// with the same block size nb, so the results are bit-identical to them:
+//
+//  LU, per panel [j, j+jb): sub-panels of kSub columns [c0, c0+w):
+//    (i)   unblocked LU of the sub-panel on rows [c0, n) (pivot search,
+//          swap inside the sub-panel, scaling, rank-1 updates);
+//    (ii)  the sub-panel's interchanges applied to all other columns;
+//    (iii) its unit-lower triangle applied to rows [c0, c0+w) of the panel
+//          columns right of it (column by column, ascending);
+//    (iv)  fused-update chain over the sub-panel's columns for all rows below
+//          it, on the panel columns right of it;
+//    then, with all of the panel's interchanges in place, U12 = L11^-1 A12
+//    with the same sub-panels ((iii) on the columns right of the panel, then
+//    the chain for the panel rows below the sub-panel), and the trailing
+//    update Rgemm(-1, 1, L21, U12) with k = jb.
+//  Each element thus receives the unblocked order's updates in the same
+//  sequence (the interchanges only move whole rows).
+//
+//  Cholesky, per diagonal block [j, j+jb): sub-blocks [c0, c0+w):
+//    unblocked Cholesky of the w x w sub-block; the block's rows below it
+//    solved against it column by column (divide, then update the sub-block's
+//    later columns); fused-update chain over its columns for the rest of the
+//    block's lower triangle.  If a diagonal fails at column c, the rows below
+//    the sub-block get the column steps before c and the rest of the block
+//    the chain over [c0, c): exactly the state the unblocked order leaves.
+//    Then L21 with the same sub-blocks, and the lower triangle of
+//    Rgemm(-1, 1, L21, L21^T).
+//
+//  Solves: the row interchanges (LU), then forward and backward substitution
+//  in blocks of kSub rows: the diagonal block column by column, then one
+//  fused-update chain over the block's columns for all rows beyond it (in
+//  descending column order for the backward pass).
+#include <hip/hip_runtime.h>
+
+#include "p32_device.hpp"
+#include "p32_gemm_tile.hpp"
+#include "p32_launch.hpp"
+
+namespace p32 {
+namespace {
+
+constexpr int kBT = NT;          // threads per workgroup (the tile routine needs NT)
+constexpr int kSub = 32;         // sub-panel / sub-block width
+constexpr uint32_t kMinus1 = 0xC0000000u;
+
+struct Shared {
+  TileLds tile;
+  unsigned long long red[kBT / 64];
+  uint32_t urow[kSub];
+  dec udec[kSub];
+  uint32_t diag[kSub];
+  int32_t piv[kSub];
+  int flag;
+};
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v, Shared& sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long b = sh.red[0];
+  for (int i = 1; i < kBT / 64; ++i) b = sh.red[i] > b ? sh.red[i] : b;
+  __syncthreads();
+  return b;
+}
+
+// every 64 x 32 tile of an m x n region through the tile routine
+template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK>
+__device__ __forceinline__ void tiles(int64_t m, int64_t n, int64_t k, const uint32_t* A, int64_t lda,
+                                      const uint32_t* B, int64_t ldb, uint32_t* C, int64_t ldc,
+                                      uint32_t alpha, uint32_t beta, Shared& sh) {
+  if (m <= 0 || n <= 0 || k <= 0) return;
+  const int64_t nr = (m + BM - 1) / BM, nc = (n + BN - 1) / BN;
+  for (int64_t t = 0; t < nr * nc; ++t)
+    gemm_tile<TA, TB, LOWER, CHAIN, REVK>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, (t / nc) * BM,
+                                          (t % nc) * BN, sh.tile);
+  __syncthreads();
+}
+
+// ---- LU ---------------------------------------------------------------------
+
+// (i) unblocked LU with partial pivoting of A[c0:n, c0:c0+w]; the swaps stay
+// inside the sub-panel; pivots go to ipiv and sh.piv; info is kept uniform.
+__device__ __forceinline__ void lu_subpanel(uint32_t* A, int64_t lda, int64_t n, int64_t c0, int w,
+                                            int32_t* ipiv, int32_t& info, Shared& sh) {
+  const int t = threadIdx.x;
+  for (int cl = 0; cl < w; ++cl) {
+    const int64_t c = c0 + cl;
+    unsigned long long best = 0ull;
+    for (int64_t i = c + t; i < n; i += kBT) {
+      const unsigned long long kk = pivot_key(A[i * lda + c], i);
+      best = kk > best ? kk : best;
+    }
+    best = block_max_u64(best, sh);
+    int64_t p = (int64_t)(0xFFFFFFFFu - (uint32_t)best);
+    if (best == 0ull || p < c || p >= n) p = c;
+    const uint32_t piv = A[p * lda + c];
+    if (piv == 0u && info == 0) info = (int32_t)(c + 1);
+    if (t == 0) {
+      ipiv[c] = (int32_t)p;
+      sh.piv[cl] = (int32_t)p;
+    }
+    __syncthreads();                               // everyone has read A[p][c]
+    if (p != c && t < w) {
+      const uint32_t x = A[c * lda + c0 + t];
+      A[c * lda + c0 + t] = A[p * lda + c0 + t];
+      A[p * lda + c0 + t] = x;
+    }
+    __syncthreads();
+    const int wq = w - cl - 1;                     // sub-panel columns right of c
+    if (t < wq) {
+      const uint32_t u = A[c * lda + c + 1 + t];
+      sh.urow[t] = u;
+      sh.udec[t] = decode(u);
+    }
+    if (piv != 0u)
+      for (int64_t i = c + 1 + t; i < n; i += kBT) A[i * lda + c] = p_div(A[i * lda + c], piv);
+    __syncthreads();
+    const int64_t cnt = (n - c - 1) * wq;
+    for (int64_t idx = t; idx < cnt; idx += kBT) {
+      const int64_t di = idx / wq;
+      const int q = (int)(idx - di * wq);
+      const int64_t i = c + 1 + di;
+      const uint32_t l = A[i * lda + c];
+      uint32_t& x = A[i * lda + c + 1 + q];
+      x = p_fms_pre(x, l, decode(l), sh.urow[q], sh.udec[q]);
+    }
+    __syncthreads();
+  }
+}
+
+// (ii) interchanges of rows c0 .. c0+w-1 (pivots in sh.piv) on every column
+// outside [c0, c0+w)
+__device__ __forceinline__ void lu_laswp(uint32_t* A, int64_t lda, int64_t n, int64_t c0, int w,
+                                         const Shared& sh) {
+  for (int64_t q = threadIdx.x; q < n - w; q += kBT) {
+    const int64_t col = q < c0 ? q : q + w;
+    for (int cl = 0; cl < w; ++cl) {
+      const int64_t p = sh.piv[cl], c = c0 + cl;
+      if (p != c) {
+        const uint32_t x = A[c * lda + col];
+        A[c * lda + col] = A[p * lda + col];
+        A[p * lda + col] = x;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// (iii) rows [c0, c0+w) of the columns [q0, q1): unit-lower solve with the
+// sub-panel's triangle, column by column in ascending order
+__device__ __forceinline__ void lu_trsm_rows(uint32_t* A, int64_t lda, int64_t c0, int w, int64_t q0,
+                                             int64_t q1) {
+  const int64_t nq = q1 - q0;
+  if (nq <= 0) return;
+  for (int cl = 0; cl + 1 < w; ++cl) {
+    const int64_t c = c0 + cl;
+    const int rows = w - cl - 1;
+    const int64_t cnt = rows * nq;
+    for (int64_t idx = threadIdx.x; idx < cnt; idx += kBT) {
+      const int64_t dr = idx / nq;
+      const int64_t q = q0 + (idx - dr * nq);
+      const int64_t r = c + 1 + dr;
+      A[r * lda + q] = p_fms(A[r * lda + q], A[r * lda + c], A[c * lda + q]);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int32_t* ipiv,
+                                          int32_t& info, Shared& sh) {
+  info = 0;
+  for (int64_t j = 0; j < n; j += nb) {
+    const int64_t jb = nb < n - j ? nb : n - j;
+    const int64_t je = j + jb;
+    for (int64_t c0 = j; c0 < je; c0 += kSub) {
+      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+      lu_subpanel(A, lda, n, c0, w, ipiv, info, sh);
+      lu_laswp(A, lda, n, c0, w, sh);
+      const int64_t r1 = c0 + w;                   // first row / column after the sub-panel
+      // the panel's columns right of the sub-panel: its rows, then all rows below
+      lu_trsm_rows(A, lda, c0, w, r1, je);
+      tiles<false, false, false, true, false>(n - r1, je - r1, w, A + r1 * lda + c0, lda,
+                                              A + c0 * lda + r1, lda, A + r1 * lda + r1, lda, 0u, 0u,
+                                              sh);
+    }
+    // U12 = L11^-1 A12, only once every interchange of the panel is in place
+    // (a later pivot may bring up a row from below the panel)
+    for (int64_t c0 = j; c0 < je && je < n; c0 += kSub) {
+      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+      const int64_t r1 = c0 + w;
+      lu_trsm_rows(A, lda, c0, w, je, n);
+      tiles<false, false, false, true, false>(je - r1, n - je, w, A + r1 * lda + c0, lda,
+                                              A + c0 * lda + je, lda, A + r1 * lda + je, lda, 0u, 0u,
+                                              sh);
+    }
+    const int64_t r0 = j + jb, rest = n - r0;
+    tiles<false, false, false, false, false>(rest, rest, jb, A + r0 * lda + j, lda, A + j * lda + r0, lda,
+                                             A + r0 * lda + r0, lda, kMinus1, kOne, sh);
+  }
+}
+
+// forward (unit lower) and backward (upper) substitution with the LU factors
+__device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_t n, const int32_t* ipiv,
+                                         uint32_t* B, int64_t ldb, int64_t nrhs, Shared& sh) {
+  const int t = threadIdx.x;
+  for (int64_t q = t; q < nrhs; q += kBT)
+    for (int64_t c = 0; c < n; ++c) {
+      const int64_t p = ipiv[c];
+      if (p != c) {
+        const uint32_t x = B[c * ldb + q];
+        B[c * ldb + q] = B[p * ldb + q];
+        B[p * ldb + q] = x;
+      }
+    }
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < n; c0 += kSub) {
+    const int w = (int)(kSub < n - c0 ? kSub : n - c0);
+    for (int cl = 0; cl + 1 < w; ++cl) {
+      const int64_t c = c0 + cl;
+      const int64_t cnt = (w - cl - 1) * nrhs;
+      for (int64_t idx = t; idx < cnt; idx += kBT) {
+        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+        const int64_t r = c + 1 + dr;
+        B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
+      }
+      __syncthreads();
+    }
+    const int64_t r1 = c0 + w;
+    tiles<false, false, false, true, false>(n - r1, nrhs, w, LU + r1 * lda + c0, lda, B + c0 * ldb, ldb,
+                                            B + r1 * ldb, ldb, 0u, 0u, sh);
+  }
+  for (int64_t c1 = n; c1 > 0; c1 -= kSub) {
+    const int64_t c0 = c1 - kSub > 0 ? c1 - kSub : 0;
+    for (int64_t c = c1 - 1; c >= c0; --c) {
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], LU[c * lda + c]);
+      __syncthreads();
+      const int64_t cnt = (c - c0) * nrhs;
+      for (int64_t idx = t; idx < cnt; idx += kBT) {
+        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+        const int64_t r = c0 + dr;
+        B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
+      }
+      __syncthreads();
+    }
+    tiles<false, false, false, true, true>(c0, nrhs, c1 - c0, LU + c0, lda, B + c0 * ldb, ldb, B, ldb, 0u,
+                                           0u, sh);
+  }
+}
+
+// ---- Cholesky -----------------------------------------------------------------
+
+// unblocked Cholesky of the w x w sub-block at A[c0][c0]; returns the failing
+// column (>= c0) or -1
+__device__ __forceinline__ int64_t chol_subblock(uint32_t* A, int64_t lda, int64_t c0, int w,
+                                                 Shared& sh) {
+  const int t = threadIdx.x;
+  for (int cl = 0; cl < w; ++cl) {
+    const int64_t c = c0 + cl;
+    if (t == 0) {
+      const uint32_t a = A[c * lda + c];
+      sh.flag = (int32_t)a <= 0;                   // non-positive or NaR
+      if (!sh.flag) A[c * lda + c] = p_sqrt(a);
+    }
+    __syncthreads();
+    if (sh.flag) return c;
+    const uint32_t d = A[c * lda + c];
+    const int rows = w - cl - 1;
+    if (t < rows) A[(c + 1 + t) * lda + c] = p_div(A[(c + 1 + t) * lda + c], d);
+    __syncthreads();
+    for (int idx = t; idx < rows * rows; idx += kBT) {
+      const int a = idx / rows, b = idx - a * rows;  // element (c+1+a, c+1+b), b <= a
+      if (b <= a) {
+        const int64_t i = c + 1 + a, q = c + 1 + b;
+        A[i * lda + q] = p_fms(A[i * lda + q], A[i * lda + c], A[q * lda + c]);
+      }
+    }
+    __syncthreads();
+  }
+  return -1;
+}
+
+// rows [r0, r1) against the sub-block's triangle at A[c0][c0] (width w):
+// column steps c0 .. c0+steps-1, each dividing column c by L[c][c] and
+// updating the later sub-block columns of those rows
+__device__ __forceinline__ void chol_trsm_rows(uint32_t* A, int64_t lda, int64_t r0, int64_t r1, int64_t c0,
+                                               int w, int steps, Shared& sh) {
+  const int t = threadIdx.x;
+  const int64_t nr = r1 - r0;
+  if (nr <= 0) return;
+  if (t < steps) sh.diag[t] = A[(c0 + t) * lda + c0 + t];
+  __syncthreads();
+  for (int cl = 0; cl < steps; ++cl) {
+    const int64_t c = c0 + cl;
+    for (int64_t r = r0 + t; r < r1; r += kBT) A[r * lda + c] = p_div(A[r * lda + c], sh.diag[cl]);
+    __syncthreads();
+    const int wq = w - cl - 1;
+    const int64_t cnt = nr * wq;
+    for (int64_t idx = t; idx < cnt; idx += kBT) {
+      const int64_t dr = idx / wq;
+      const int64_t q = c + 1 + (idx - dr * wq);
+      const int64_t r = r0 + dr;
+      A[r * lda + q] = p_fms(A[r * lda + q], A[r * lda + c], A[q * lda + c]);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int32_t& info,
+                                            Shared& sh) {
+  info = 0;
+  for (int64_t j = 0; j < n; j += nb) {
+    const int64_t jb = nb < n - j ? nb : n - j;
+    const int64_t je = j + jb;
+    for (int64_t c0 = j; c0 < je; c0 += kSub) {
+      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+      const int64_t r1 = c0 + w;
+      const int64_t fail = chol_subblock(A, lda, c0, w, sh);
+      const int steps = fail < 0 ? w : (int)(fail - c0);
+      chol_trsm_rows(A, lda, r1, je, c0, w, steps, sh);
+      tiles<false, true, true, true, false>(je - r1, je - r1, steps, A + r1 * lda + c0, lda,
+                                            A + r1 * lda + c0, lda, A + r1 * lda + r1, lda, 0u, 0u, sh);
+      if (fail >= 0) {
+        info = (int32_t)(fail + 1);
+        return;
+      }
+    }
+    const int64_t rest = n - je;
+    if (rest <= 0) continue;
+    for (int64_t c0 = j; c0 < je; c0 += kSub) {
+      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+      const int64_t c1 = c0 + w;
+      chol_trsm_rows(A, lda, je, n, c0, w, w, sh);
+      tiles<false, true, false, true, false>(rest, je - c1, w, A + je * lda + c0, lda, A + c1 * lda + c0,
+                                             lda, A + je * lda + c1, lda, 0u, 0u, sh);
+    }
+    tiles<false, true, true, false, false>(rest, rest, jb, A + je * lda + j, lda, A + je * lda + j, lda,
+                                           A + je * lda + je, lda, kMinus1, kOne, sh);
+  }
+}
+
+__device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64_t n, uint32_t* B,
+                                           int64_t ldb, int64_t nrhs, Shared& sh) {
+  const int t = threadIdx.x;
+  for (int64_t c0 = 0; c0 < n; c0 += kSub) {
+    const int w = (int)(kSub < n - c0 ? kSub : n - c0);
+    for (int cl = 0; cl < w; ++cl) {
+      const int64_t c = c0 + cl;
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
+      __syncthreads();
+      const int64_t cnt = (w - cl - 1) * nrhs;
+      for (int64_t idx = t; idx < cnt; idx += kBT) {
+        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+        const int64_t r = c + 1 + dr;
+        B[r * ldb + q] = p_fms(B[r * ldb + q], L[r * lda + c], B[c * ldb + q]);
+      }
+      __syncthreads();
+    }
+    const int64_t r1 = c0 + w;
+    tiles<false, false, false, true, false>(n - r1, nrhs, w, L + r1 * lda + c0, lda, B + c0 * ldb, ldb,
+                                            B + r1 * ldb, ldb, 0u, 0u, sh);
+  }
+  for (int64_t c1 = n; c1 > 0; c1 -= kSub) {
+    const int64_t c0 = c1 - kSub > 0 ? c1 - kSub : 0;
+    for (int64_t c = c1 - 1; c >= c0; --c) {
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
+      __syncthreads();
+      const int64_t cnt = (c - c0) * nrhs;
+      for (int64_t idx = t; idx < cnt; idx += kBT) {
+        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+        const int64_t r = c0 + dr;
+        B[r * ldb + q] = p_fms(B[r * ldb + q], L[c * lda + r], B[c * ldb + q]);
+      }
+      __syncthreads();
+    }
+    // rows above the block: coefficient L[c][r] = op(A)(r, c) with op = transpose
+    tiles<true, false, false, true, true>(c0, nrhs, c1 - c0, L + c0 * lda, lda, B + c0 * ldb, ldb, B, ldb,
+                                          0u, 0u, sh);
+  }
+}
+
+// ---- the persistent kernel ------------------------------------------------------
+
+struct Batch {
+  int32_t count;
+  int32_t max_n;
+  int32_t nb;
+  const int32_t* n;
+  uint32_t* const* A;
+  const int64_t* lda;
+  int32_t* const* ipiv;
+  const int32_t* nrhs;
+  uint32_t* const* B;
+  const int64_t* ldb;
+  int32_t* info;
+};
+
+// KIND 0: LU, 1: Cholesky.  FACTOR / SOLVE select the phases; with both, a
+// failed factorisation (info > 0) skips the solve.
+// (Everything is inlined into the kernel and the register budget is two
+// waves per SIMD: the tile routine alone needs about 124 VGPRs, and with the
+// kernel's own live state a tighter budget spills inside its inner loop.)
+template <int KIND, bool FACTOR, bool SOLVE>
+__global__ void __launch_bounds__(kBT, 2) vbatched_kernel(Batch bt) {
+  __shared__ Shared sh;
+  for (int64_t idx = blockIdx.x; idx < bt.count; idx += gridDim.x) {
+    const int64_t n = bt.n[idx];
+    uint32_t* A = bt.A[idx];
+    const int64_t lda = bt.lda[idx];
+    int32_t* ipiv = KIND == 0 ? bt.ipiv[idx] : nullptr;
+    const int64_t nrhs = SOLVE ? bt.nrhs[idx] : 0;
+    uint32_t* B = SOLVE ? bt.B[idx] : nullptr;
+    const int64_t ldb = SOLVE ? bt.ldb[idx] : 1;
+    int32_t status = 0;
+    if (n < 0 || n > bt.max_n) status = -1;
+    else if (n > 0 && A == nullptr) status = -2;
+    else if (lda < (n > 1 ? n : 1)) status = -3;
+    else if (KIND == 0 && n > 0 && ipiv == nullptr) status = -4;
+    else if (SOLVE && nrhs < 0) status = -5;
+    else if (SOLVE && n > 0 && nrhs > 0 && B == nullptr) status = -6;
+    else if (SOLVE && ldb < (nrhs > 1 ? nrhs : 1)) status = -7;
+    if (status == 0 && FACTOR) {
+      if (KIND == 0) lu_factor(A, lda, n, bt.nb, ipiv, status, sh);
+      else chol_factor(A, lda, n, bt.nb, status, sh);
+    }
+    if (SOLVE && status == 0 && n > 0 && nrhs > 0) {
+      if (KIND == 0) lu_solve(A, lda, n, ipiv, B, ldb, nrhs, sh);
+      else chol_solve(A, lda, n, B, ldb, nrhs, sh);
+    }
+    if (threadIdx.x == 0) bt.info[idx] = status;
+    __syncthreads();
+  }
+}
+
+template <int KIND, bool FACTOR, bool SOLVE>
+int launch_kernel(hipStream_t s, const Batch& bt) {
+  const void* fn = reinterpret_cast<const void*>(&vbatched_kernel<KIND, FACTOR, SOLVE>);
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBT, 0);
+  if (e != hipSuccess) return -1000 - (int)e;
+  int64_t grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+  if (grid > bt.count) grid = bt.count;
+  hipLaunchKernelGGL((vbatched_kernel<KIND, FACTOR, SOLVE>), dim3((unsigned)grid), dim3(kBT), 0, s, bt);
+  return launch_status();
+}
+
+}  // namespace
+
+int launch_vbatched(hipStream_t s, int kind, bool factor, bool solve, int32_t count, int32_t max_n,
+                    int64_t nb, const int32_t* n, uint32_t* const* A, const int64_t* lda,
+                    int32_t* const* ipiv, const int32_t* nrhs, uint32_t* const* B, const int64_t* ldb,
+                    int32_t* info) {
+  if (count == 0) return 0;
+  Batch bt{count, max_n, (int32_t)nb, n, A, lda, ipiv, nrhs, B, ldb, info};
+  if (kind == 0) {
+    if (factor && solve) return launch_kernel<0, true, true>(s, bt);
+    if (factor) return launch_kernel<0, true, false>(s, bt);
+    return launch_kernel<0, false, true>(s, bt);
+  }
+  if (factor && solve) return launch_kernel<1, true, true>(s, bt);
+  if (factor) return launch_kernel<1, true, false>(s, bt);
+  return launch_kernel<1, false, true>(s, bt);
+}
+
+}  // namespace p32

@@ -1,12 +1,13 @@
 // p32_gemm.hip -- Posit(32,2) Rgemm, C = alpha*op(A)*op(B) + beta*C
 // (paper, Section 3, Eq. (2); GPU blocking through shared memory, Section 3.2).
 //
-// One workgroup of 256 threads owns a 64 x 64 tile of C; each thread owns a
-// 4 x 4 micro-tile whose 16 accumulators stay decoded in registers (window
-// form) for the whole k loop.  Per k-tile of 16, the workgroup reads op(A) and
-// op(B) tiles with coalesced loads, decodes every element once into LDS as
-// (significand, scale), and each thread then runs the multiply -> round ->
-// add -> round chain for its 16 outputs, strictly in ascending k.  NaR inputs
+// One workgroup of 256 threads owns a BM x BN = 64 x 32 tile of C; each
+// thread owns a TM x TN = 4 x 2 micro-tile whose 8 accumulators stay decoded
+// in registers (window form) for the whole k loop.  Per k-tile of 16, the
+// workgroup reads op(A) and op(B) tiles with coalesced loads, decodes every
+// element once into LDS as (significand, scale), and each thread then runs
+// the multiply -> round -> add -> round chain for its 8 outputs, strictly in
+// ascending k.  NaR inputs
 // are recorded per row of op(A) and per column of op(B) (a NaR anywhere in a
 // row/column makes the whole output row/column NaR) and replaced by 1.0 in LDS
 // so the integer pipeline never sees them.  Rows beyond m and columns beyond
@@ -20,305 +21,23 @@
 #include <hip/hip_runtime.h>
 
 #include "p32_device.hpp"
+#include "p32_gemm_tile.hpp"
 #include "p32_launch.hpp"
 
 namespace p32 {
 
-#ifndef P32_GEMM_MIN_WAVES
-#define P32_GEMM_MIN_WAVES 4      // minimum waves per SIMD the register budget must allow
-#endif
-
-#ifndef P32_GEMM_TM
-#define P32_GEMM_TM 4             // rows of C per thread
-#endif
-#ifndef P32_GEMM_TN
-#define P32_GEMM_TN 2             // columns of C per thread
-#endif
-
-constexpr int TM = P32_GEMM_TM, TN = P32_GEMM_TN, NT = 256, BK = 16;
-constexpr int BM = 16 * TM, BN = 16 * TN;   // 16 x 16 threads per workgroup
-constexpr unsigned GROUP_M = 8;             // tile rows per group of the tile order
-constexpr int EB = 8192 + 128;           // exponent bias inside the kernel
-constexpr int kEZeroB = kEZero + EB;     // biased exponent of zero (> 0)
-
-// ---- rare path: exact multiply-add for one element (unbiased interface) ----
-__device__ __noinline__ win madd_slow(win acc, int32_t a8, int32_t sca, int32_t b4, int32_t scb) {
-  return add_slow(acc, mul_slow(a8, sca, b4, scb));
-}
-
-// epilogue for one element: r = alpha*acc, then r + beta*c
-__device__ __noinline__ uint32_t gemm_epilogue(win acc, int nar, uint32_t alpha, uint32_t beta,
-                                               uint32_t c) {
-  uint32_t r;
-  if (nar || alpha == kNaR) {
-    r = kNaR;
-  } else {
-    const uint32_t a = encode_exact(acc);
-    r = alpha == kOne ? a : mul_general(decode(alpha), decode(a));
-  }
-  if (beta != 0u) {
-    if (r == kNaR || beta == kNaR || c == kNaR) return kNaR;
-    const uint32_t t = mul_general(decode(beta), decode(c));
-    r = add_general(win_of(r), win_of(t));
-  }
-  return r;
-}
-
-__device__ __forceinline__ win unbias(win w) {
-  win u;
-  u.h = w.h;
-  u.e = w.h ? w.e - EB : kEZero;
-  return u;
-}
-
-__device__ __forceinline__ win bias(win u) {
-  win w;
-  w.h = u.h;
-  w.e = u.h ? u.e + EB : kEZeroB;
-  return w;
-}
-
-// ---- checked fast path (any operands; flags what it does not cover) --------
-// staged operand a = (s_a << 3, sc_a + EB + 4), b = (s_b << 2, sc_b)
-__device__ __forceinline__ bool mul_checked(int2 a, int2 b, win& out) {
-  const int64_t P = (int64_t)a.x * (int64_t)b.x;       // |P| in [2^59, 2^61)
-  const int cnt = ffbh_i32((int32_t)(P >> 32));
-  const int c3 = cnt - 3;
-  const int eb = a.y + b.y - cnt;                      // biased scale
-  const int sc = eb - EB;
-  out.h = round_h2(fold_sticky((uint64_t)P << (c3 & 63)), sc).h;
-  out.e = eb;
-  return ((unsigned)c3 < 3u) & scale_ok(sc);
-}
-
-__device__ __forceinline__ bool add_checked(win a, win b, win& out) {
-  const int E = a.e > b.e ? a.e : b.e;
-  const int da = min(E - a.e, 63), db = min(E - b.e, 63);
-  const int64_t S = (((int64_t)a.h << 32) >> da) + (((int64_t)b.h << 32) >> db);
-  const int cnt = ffbh_i32((int32_t)(S >> 32));
-  const int c3 = cnt - 3;
-  const int eb = E + 4 - cnt;
-  const int sc = eb - EB;
-  out.h = round_h2(fold_sticky((uint64_t)S << (c3 & 63)), sc).h;
-  out.e = eb;
-  return ((unsigned)c3 < 29u) & scale_ok(sc);
-}
-
-// ---- unchecked fast path (operands proven in range for the whole k-tile) ---
-// The rounding parameters come from the LDS table; exponent differences use
-// saturating subtraction and the one test left covers cancellation (c3 < 0)
-// and alignments of 64 bits or more, which go to the exact path.
-__device__ __forceinline__ win mul_unchecked(int2 a, int2 b, const uint2* __restrict__ lut) {
-  const int64_t P = (int64_t)a.x * (int64_t)b.x;
-  const int cnt = ffbh_i32((int32_t)(P >> 32));
-  const int eb = a.y + b.y - cnt;
-  const uint2 rp = lut[eb & 255];
-  win w;
-  w.h = round_lut(fold_sticky((uint64_t)P << ((cnt - 3) & 63)), rp);
-  w.e = eb;
-  return w;
-}
-
-__device__ __forceinline__ win add_unchecked(win a, win b, const uint2* __restrict__ lut,
-                                             uint32_t& badbits) {
-  const uint32_t db = __builtin_elementwise_sub_sat((uint32_t)a.e, (uint32_t)b.e);
-  const uint32_t da = __builtin_elementwise_sub_sat((uint32_t)b.e, (uint32_t)a.e);
-  const int E = b.e + (int)db;                          // max(a.e, b.e)
-  const int64_t S = (((int64_t)a.h << 32) >> da) + (((int64_t)b.h << 32) >> db);
-  const int cnt = ffbh_i32((int32_t)(S >> 32));
-  const int c3 = cnt - 3;
-  badbits |= da | db | (uint32_t)c3;                    // > 63 means: exact path
-  const int eb = E + 4 - cnt;
-  const uint2 rp = lut[eb & 255];
-  win w;
-  w.h = round_lut(fold_sticky((uint64_t)S << (c3 & 63)), rp);
-  w.e = eb;
-  return w;
-}
-
-// One k step for the thread's TM x TN accumulators.  Flagged lanes redo the
-// whole step on the exact path.
-template <bool CHECKED>
-__device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restrict__ Arow,
-                                       const int2* __restrict__ Brow, const uint2* __restrict__ lut,
-                                       int tx, int ty) {
-  int2 a[TM], b[TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = Arow[ty * TM + i];
-#pragma unroll
-  for (int j = 0; j < TN; ++j) b[j] = Brow[tx * TN + j];
-  win nacc[TM][TN];
-  bool bad = false;
-  uint32_t badbits = 0;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      if (CHECKED) {
-        win pr;
-        bad |= !mul_checked(a[i], b[j], pr);
-        bad |= !add_checked(acc[i][j], pr, nacc[i][j]);
-      } else {
-        const win pr = mul_unchecked(a[i], b[j], lut);
-        nacc[i][j] = add_unchecked(acc[i][j], pr, lut, badbits);
-      }
-    }
-  if (!CHECKED) bad = badbits > 63u;
-  if (bad) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        nacc[i][j] = bias(madd_slow(unbias(acc[i][j]), a[i].x, a[i].y - EB - 4, b[j].x, b[j].y));
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = nacc[i][j];
-}
-
-// LOWER: only the lower triangle (row >= column) of C is computed and written
-// (the trailing update of a Cholesky factorisation).  skip: when non-null and
-// nonzero on entry, the kernel does nothing (a failed factorisation step).
-// CHAIN: instead of Rgemm, each C_ij gets the chain of fused updates
-// C_ij = rnd(C_ij - rnd(a_ip * b_pj)) for p = 0, 1, ..., k-1 in order (the
-// unblocked factorisations' rank-1 updates, applied k columns at a time); it
-// runs as the same k loop with the accumulators starting at C and op(A)
-// negated (rnd(-x) = -rnd(x) exactly), and alpha and beta are not used.
+// One tile per workgroup.  skip: when non-null and nonzero on entry, the
+// kernel does nothing (a failed factorisation step).
 template <bool TA, bool TB, bool LOWER, bool CHAIN>
 __global__ void __launch_bounds__(NT, P32_GEMM_MIN_WAVES)
 gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
             const uint32_t* __restrict__ B, int64_t ldb, uint32_t* __restrict__ C, int64_t ldc,
             uint32_t alpha, uint32_t beta, const int32_t* __restrict__ skip) {
+  __shared__ TileLds sm;
   if (skip != nullptr && *skip != 0) return;
-  __shared__ int2 As[BK][BM];   // (s << 3, scale + EB + 4) of op(A)(i0 + i, p0 + p)
-  __shared__ int2 Bs[BK][BN];   // (s << 2, scale) of op(B)(p0 + p, j0 + j)
-  __shared__ uint2 lut[256];    // rounding parameters of scales -128..127
-  __shared__ int rowNaR[BM], colNaR[BN];
-
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  // Tile order.  The dispatcher places workgroup g on XCD g % 8, and each XCD
-  // has its own L2, so consecutive tiles are handed to the same XCD: XCD x
-  // takes the x-th eighth of the tile sequence.  The sequence walks groups of
-  // GROUP_M tile rows column by column, so the tiles that are resident on an
-  // XCD at one time form a compact block of C and share their A and B panels
-  // in that XCD's L2.
-  const unsigned nrow = (unsigned)((m + BM - 1) / BM), ncol = (unsigned)((n + BN - 1) / BN);
-  const unsigned G = nrow * ncol;
-  unsigned g = blockIdx.x;
-  if (G % 8u == 0u) g = (g % 8u) * (G / 8u) + g / 8u;
-  const unsigned per_group = GROUP_M * ncol;
-  const unsigned first_row = (g / per_group) * GROUP_M;
-  const unsigned rows_here = min(nrow - first_row, (unsigned)GROUP_M);
-  const unsigned in_group = g % per_group;
-  const int64_t i0 = (int64_t)(first_row + in_group % rows_here) * BM;
-  const int64_t j0 = (int64_t)(in_group / rows_here) * BN;
-  if (LOWER && i0 + BM - 1 < j0) return;          // tile entirely above the diagonal
-  if (tid < BM) rowNaR[tid] = 0;
-  if (tid < BN) colNaR[tid] = 0;
-  lut[tid] = round_params(tid - 128);   // NT == 256 entries
-
-  win acc[TM][TN];
-  uint32_t cnar = 0;            // CHAIN: bit i*TN+j set when C_ij starts as NaR
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      acc[i][j].h = 0;
-      acc[i][j].e = kEZeroB;
-      if (CHAIN) {
-        const int64_t gi = i0 + ty * TM + i, gj = j0 + tx * TN + j;
-        if (gi < m && gj < n && !(LOWER && gj > gi)) {
-          const uint32_t c = C[gi * ldc + gj];
-          if (c == kNaR) cnar |= 1u << (i * TN + j);
-          else acc[i][j] = bias(win_of(c));
-        }
-      }
-    }
-
-  for (int64_t p0 = 0; p0 < k; p0 += BK) {
-    int my_ok = 1;
-    __syncthreads();
-#pragma unroll
-    for (int l = 0; l < (BM * BK) / NT; ++l) {
-      const int idx = tid + l * NT;
-      const int ii = TA ? idx % BM : idx / BK;
-      const int pp = TA ? idx / BM : idx % BK;
-      const int64_t gi = i0 + ii, gp = p0 + pp;
-      uint32_t v;
-      if (gp >= k) v = 0u;
-      else if (gi >= m) v = kOne;
-      else v = TA ? A[gp * lda + gi] : A[gi * lda + gp];
-      if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
-      const dec d = decode(v);
-      my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
-      As[pp][ii] = make_int2((CHAIN ? -d.s : d.s) * 8, d.sc + EB + 4);
-    }
-#pragma unroll
-    for (int l = 0; l < (BN * BK) / NT; ++l) {
-      const int idx = tid + l * NT;
-      const int jj = TB ? idx / BK : idx % BN;
-      const int pp = TB ? idx % BK : idx / BN;
-      const int64_t gj = j0 + jj, gp = p0 + pp;
-      uint32_t v;
-      if (gp >= k) v = 0u;
-      else if (gj >= n) v = kOne;
-      else v = TB ? B[gj * ldb + gp] : B[gp * ldb + gj];
-      if (v == kNaR) { colNaR[jj] = 1; v = kOne; }
-      const dec d = decode(v);
-      my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
-      Bs[pp][jj] = make_int2(d.s * 4, d.sc);
-    }
-    // Block-uniform choice of the inner loop for this k-tile.  The unchecked
-    // loop is exact when every staged operand is nonzero with scale in
-    // [-53, 49] (products then have scales in [-106, 99]) and every
-    // accumulator is zero or has scale in [-106, 100].  Sums then keep
-    // scales in [-108, 104], inside the fast range: with |p| >= 2^-106, a
-    // sum acc + p either has |acc| < |p|/2 and so |sum| > 2^-107, or both
-    // terms are multiples of 2^-108 and a nonzero sum is >= 2^-108; and 16
-    // products below 2^100 cannot lift |acc| < 2^101 past 2^105.  Left to
-    // test: cancellation to zero or by more than 28 bits, and alignment
-    // shifts of 64 bits or more (e.g. a zero accumulator).
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        my_ok &= (acc[i][j].h == 0) | ((unsigned)(acc[i][j].e - EB + 106) <= 206u);
-    const bool safe = __syncthreads_and(my_ok);
-
-    int p = 0;
-    if (p0 == 0) {        // first step: accumulators not yet tested, use the checked path
-      k_step<true>(acc, As[0], Bs[0], lut, tx, ty);
-      p = 1;
-    }
-    if (safe) {
-#pragma unroll 1
-      for (; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
-    } else {
-#pragma unroll 1
-      for (; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
-    }
-  }
-  __syncthreads();
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    const int64_t gi = i0 + ty * TM + i;
-    if (gi >= m) continue;
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t gj = j0 + tx * TN + j;
-      if (gj >= n || (LOWER && gj > gi)) continue;
-      const int nar = rowNaR[ty * TM + i] | colNaR[tx * TN + j];
-      if (CHAIN) {
-        C[gi * ldc + gj] = nar || ((cnar >> (i * TN + j)) & 1u) ? kNaR : encode_exact(unbias(acc[i][j]));
-        continue;
-      }
-      const uint32_t c = beta ? C[gi * ldc + gj] : 0u;
-      C[gi * ldc + gj] = gemm_epilogue(unbias(acc[i][j]), nar, alpha, beta, c);
-    }
-  }
+  int64_t i0, j0;
+  tile_origin(m, n, blockIdx.x, i0, j0);
+  gemm_tile<TA, TB, LOWER, CHAIN>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, i0, j0, sm);
 }
 
 // alpha == 0 or k == 0: C = (beta == 0) ? 0 : beta*C

@@ -36,4 +36,10 @@ int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
 int launch_potrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint32_t* B,
                  int64_t ldb);
 
+// variable-size batch: kind 0 LU, 1 Cholesky; factor and/or solve phases
+int launch_vbatched(hipStream_t s, int kind, bool factor, bool solve, int32_t count, int32_t max_n,
+                    int64_t nb, const int32_t* n, uint32_t* const* A, const int64_t* lda,
+                    int32_t* const* ipiv, const int32_t* nrhs, uint32_t* const* B, const int64_t* ldb,
+                    int32_t* info);
+
 }  // namespace p32

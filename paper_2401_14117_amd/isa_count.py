@@ -22,7 +22,7 @@ MADDS_PER_STEP = 8    # TM * TN of the kernel
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("p32_device.hpp", "p32_gemm.hip"):
+    for f in ("p32_device.hpp", "p32_gemm_tile.hpp", "p32_gemm.hip"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

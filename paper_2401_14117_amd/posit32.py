@@ -52,8 +52,16 @@ def lib() -> ctypes.CDLL:
     L.posit32_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64]
     L.posit32_potrf.argtypes = [vp, i64, i64, vp, i64, vp]
     L.posit32_potrs.argtypes = [vp, i64, i64, vp, i64, vp, i64]
+    L.posit32_getrf_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
+    L.posit32_getrs_vbatched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_gesv_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_potrf_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
+    L.posit32_potrs_vbatched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_posv_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]
     for f in (L.posit32_from_f64, L.posit32_to_f64, L.posit32_elementwise, L.posit32_getrf,
-              L.posit32_getrs, L.posit32_potrf, L.posit32_potrs):
+              L.posit32_getrs, L.posit32_potrf, L.posit32_potrs, L.posit32_getrf_vbatched,
+              L.posit32_getrs_vbatched, L.posit32_gesv_vbatched, L.posit32_potrf_vbatched,
+              L.posit32_potrs_vbatched, L.posit32_posv_vbatched):
         f.restype = i32
     _lib = L
     return L
@@ -119,6 +127,10 @@ def from_f64(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> t
     x = x.contiguous()
     if out is None:
         out = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    else:
+        _is_i32_cuda(out)
+        if out.numel() != x.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor with x's number of elements")
     _check(lib().posit32_from_f64(_stream(stream), x.numel(), _ptr(x), _ptr(out)), "posit32_from_f64")
     return out
 
@@ -205,3 +217,94 @@ def potrs(L: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
     _check(lib().posit32_potrs(_stream(stream), n, B2.shape[1], _ptr(L), _ld(L), _ptr(B2), _ld(B2)),
            "posit32_potrs")
     return B
+
+
+class VBatch:
+    """Device-side description of a variable-size batch (the pointer, size and
+    leading-dimension arrays of the *_vbatched entry points), built once from
+    lists of tensors so that repeated calls only launch.
+
+    As: n_i x n_i int32 device matrices (row-major); Bs: optional n_i x nrhs_i
+    right-hand sides; lu: allocate pivot vectors for the LU calls.  The
+    tensors stay owned by the caller and must outlive the batch."""
+
+    def __init__(self, As, Bs=None, lu: bool = True, device=None):
+        dev = device if device is not None else (As[0].device if As else torch.device("cuda"))
+        self.count = len(As)
+        ns = []
+        for A in As:
+            ns.append(_square(A))
+        self.max_n = max(ns) if ns else 0
+        self.n = torch.tensor(ns, dtype=torch.int32, device=dev)
+        self.A = torch.tensor([A.data_ptr() for A in As], dtype=torch.int64, device=dev)
+        self.lda = torch.tensor([_ld(A) for A in As], dtype=torch.int64, device=dev)
+        self.info = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        self.ipivs = None
+        self.ipiv = None
+        if lu:
+            self.ipivs = [torch.empty(max(k, 1), dtype=torch.int32, device=dev) for k in ns]
+            self.ipiv = torch.tensor([p.data_ptr() for p in self.ipivs], dtype=torch.int64, device=dev)
+        self.nrhs = self.B = self.ldb = None
+        if Bs is not None:
+            if len(Bs) != self.count:
+                raise ValueError("one right-hand side per matrix")
+            B2 = [_rhs(B, k) for B, k in zip(Bs, ns)]
+            self.nrhs = torch.tensor([b.shape[1] for b in B2], dtype=torch.int32, device=dev)
+            self.B = torch.tensor([b.data_ptr() for b in B2], dtype=torch.int64, device=dev)
+            self.ldb = torch.tensor([_ld(b) for b in B2], dtype=torch.int64, device=dev)
+        self._keep = (As, Bs)
+
+    def _need_b(self):
+        if self.B is None:
+            raise ValueError("this batch has no right-hand sides")
+
+    def _need_piv(self):
+        if self.ipiv is None:
+            raise ValueError("this batch was built without pivot vectors (lu=False)")
+
+    def getrf(self, nb: int = 256, stream=None) -> torch.Tensor:
+        self._need_piv()
+        _check(lib().posit32_getrf_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
+                                            _ptr(self.A), _ptr(self.lda), _ptr(self.ipiv),
+                                            _ptr(self.info)), "posit32_getrf_vbatched")
+        return self.info
+
+    def getrs(self, stream=None) -> torch.Tensor:
+        self._need_piv()
+        self._need_b()
+        _check(lib().posit32_getrs_vbatched(_stream(stream), self.count, self.max_n, _ptr(self.n),
+                                            _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
+                                            _ptr(self.ipiv), _ptr(self.B), _ptr(self.ldb),
+                                            _ptr(self.info)), "posit32_getrs_vbatched")
+        return self.info
+
+    def gesv(self, nb: int = 256, stream=None) -> torch.Tensor:
+        self._need_piv()
+        self._need_b()
+        _check(lib().posit32_gesv_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
+                                           _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
+                                           _ptr(self.ipiv), _ptr(self.B), _ptr(self.ldb),
+                                           _ptr(self.info)), "posit32_gesv_vbatched")
+        return self.info
+
+    def potrf(self, nb: int = 256, stream=None) -> torch.Tensor:
+        _check(lib().posit32_potrf_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
+                                            _ptr(self.A), _ptr(self.lda), _ptr(self.info)),
+               "posit32_potrf_vbatched")
+        return self.info
+
+    def potrs(self, stream=None) -> torch.Tensor:
+        self._need_b()
+        _check(lib().posit32_potrs_vbatched(_stream(stream), self.count, self.max_n, _ptr(self.n),
+                                            _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
+                                            _ptr(self.B), _ptr(self.ldb), _ptr(self.info)),
+               "posit32_potrs_vbatched")
+        return self.info
+
+    def posv(self, nb: int = 256, stream=None) -> torch.Tensor:
+        self._need_b()
+        _check(lib().posit32_posv_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
+                                           _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
+                                           _ptr(self.B), _ptr(self.ldb), _ptr(self.info)),
+               "posit32_posv_vbatched")
+        return self.info

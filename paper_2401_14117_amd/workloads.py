@@ -154,3 +154,36 @@ def elementwise_range(n: int, rng_name: str) -> tuple[np.ndarray, np.ndarray]:
     p = rng.uniform(a, b, n)
     q = rng.uniform(a, b, n)
     return p, q
+
+
+@dataclass
+class BatchCase:
+    name: str
+    kind: str                 # "lu" or "chol"
+    n: np.ndarray             # int64 [count]
+    nrhs: np.ndarray          # int64 [count]
+    seed: int
+
+
+def batch_sizes(count: int = 20000, seed: int = 6000) -> tuple[np.ndarray, np.ndarray]:
+    """Sizes of the batched workload: n = round(exp(U(ln 16, ln 512))) and
+    nrhs = integers(1, 16, inclusive), drawn in that order."""
+    rng = np.random.default_rng(seed)
+    n = np.round(np.exp(rng.uniform(np.log(16), np.log(512), count))).astype(np.int64)
+    nrhs = rng.integers(1, 16, size=count, endpoint=True).astype(np.int64)
+    return n, nrhs
+
+
+def batch_matrices(kind: str, n: np.ndarray, nrhs: np.ndarray, seed: int = 6000, start: int = 0,
+                   stop: int | None = None):
+    """Yield (i, A, B) for systems start..stop-1 of the batched workload.  System
+    i draws from its own generator seeded (seed, i): LU entries uniform[-1, 1];
+    Cholesky A = M M^T / n + I with M uniform[-1, 1]; B = A * ones(n, nrhs)."""
+    stop = len(n) if stop is None else stop
+    for i in range(start, stop):
+        rng = np.random.default_rng([seed, i])
+        k = int(n[i])
+        M = rng.uniform(-1.0, 1.0, (k, k))
+        A = M if kind == "lu" else M @ M.T / k + np.eye(k)
+        B = A @ np.ones((k, int(nrhs[i])))
+        yield i, A, B

@@ -71,3 +71,35 @@ def test_other_argument_errors(L):
     assert L.posit32_elementwise(None, 0, -4, 8, 8, 8) == -3
     assert L.posit32_elementwise(None, 0, 4, 8, None, 8) == -5
     assert L.posit32_from_f64(None, 0, None, None) == 0
+
+
+def test_factorisation_argument_errors(L):
+    # validated on the host before anything is launched (no GPU needed)
+    assert L.posit32_getrf(None, -1, 256, 8, 1, 8, 8) == -2
+    assert L.posit32_getrf(None, 4, 0, 8, 4, 8, 8) == -3
+    assert L.posit32_getrf(None, 4, 257, 8, 4, 8, 8) == -3
+    assert L.posit32_getrf(None, 4, 64, None, 4, 8, 8) == -4
+    assert L.posit32_getrf(None, 4, 64, 8, 3, 8, 8) == -5
+    assert L.posit32_getrf(None, 4, 64, 8, 4, None, 8) == -6
+    assert L.posit32_getrf(None, 4, 64, 8, 4, 8, None) == -7
+    assert L.posit32_getrs(None, 4, -1, 8, 4, 8, 8, 1) == -3
+    assert L.posit32_getrs(None, 4, 2, 8, 4, 8, 8, 1) == -8
+    assert L.posit32_potrf(None, 4, 64, 8, 4, None) == -6
+    assert L.posit32_potrs(None, 4, 2, 8, 4, None, 2) == -6
+
+
+def test_vbatched_argument_errors(L):
+    # count, max_n, nb and null arrays are checked on the host; count = 0 is a no-op
+    assert L.posit32_getrf_vbatched(None, -1, 8, 256, 8, 8, 8, 8, 8) == -2
+    assert L.posit32_getrf_vbatched(None, 1, -1, 256, 8, 8, 8, 8, 8) == -3
+    assert L.posit32_getrf_vbatched(None, 1, 1 << 24, 256, 8, 8, 8, 8, 8) == -3
+    assert L.posit32_getrf_vbatched(None, 1, 8, 0, 8, 8, 8, 8, 8) == -4
+    assert L.posit32_getrf_vbatched(None, 1, 8, 256, None, 8, 8, 8, 8) == -5
+    assert L.posit32_getrf_vbatched(None, 1, 8, 256, 8, 8, 8, None, 8) == -5
+    assert L.posit32_gesv_vbatched(None, 1, 8, 256, 8, None, 8, 8, 8, 8, 8, 8) == -5
+    assert L.posit32_posv_vbatched(None, 1, 8, 300, 8, 8, 8, 8, 8, 8, 8) == -4
+    assert L.posit32_potrs_vbatched(None, 1, 8, 8, 8, 8, 8, None, 8, 8) == -5
+    assert L.posit32_getrs_vbatched(None, 1, 8, 8, 8, 8, 8, 8, 8, 8, None) == -5
+    assert L.posit32_potrf_vbatched(None, 0, 0, 256, None, None, None, None) == 0
+    assert L.posit32_gesv_vbatched(None, 0, 0, 256, None, None, None, None, None, None, None,
+                                   None) == 0

@@ -283,6 +283,8 @@ def run_batch_bench(name: str, args, dev) -> dict:
     pops = float(np.sum(fac * n.astype(np.float64) ** 3))
 
     # one system at a time through the single-matrix entry points, on a sample
+    if args.single_count <= 0:
+        return _batch_result(name, kind, count, kms, pops, info, setup_s, None, None, args)
     rs = np.random.default_rng(6001)
     sample = np.sort(rs.choice(count, size=min(args.single_count, count), replace=False))
     A.copy_(A0)
@@ -336,6 +338,10 @@ def run_batch_bench(name: str, args, dev) -> dict:
         cpu = {"value": round(done / el, 3), "unit": "solves/s", "cores": O.num_threads(),
                "kind": "oracle", "sample": f"first {done} systems of the batch (in generation order)"}
 
+    return _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args)
+
+
+def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args) -> dict:
     return {
         "metric": f"Posit32 batched {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s",
         "value": round(count / (kms * 1e-3), 1),
@@ -416,7 +422,7 @@ def main() -> int:
     ap.add_argument("--ew-n", type=int, default=1 << 26, help="elements of the elementwise workloads")
     ap.add_argument("--batch-count", type=int, default=20000, help="systems of the batched workloads")
     ap.add_argument("--single-count", type=int, default=300,
-                    help="sampled systems timed one at a time beside the batched workloads")
+                    help="sampled systems timed one at a time beside the batched workloads (0: skip)")
     ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")

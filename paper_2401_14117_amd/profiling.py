@@ -1,4 +1,5 @@
-"""Summaries of rocprofv3 output for the Rgemm kernel (a reporting utility).
+"""Summaries of rocprofv3 output (a reporting utility): the Rgemm kernel's
+time and HBM traffic, and per-kernel time tables of other traced commands.
 
 rocprofv3 is run on the MI355X machine by the commands recorded in each summary;
 this module only reads the CSV files it writes:
@@ -74,15 +75,15 @@ def summarize(args) -> None:
         "Commands (run on the MI355X box from /tmp, REPO = the repository root):",
         "",
         "```",
-        f"rocprofv3 --kernel-trace --output-format csv -d $REPO/gpurun_out/trace -o trace -- "
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof/trace -o trace -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 2 --warmup 1 --cpu-budget 0",
-        f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/fetch -o fetch -- "
+        f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/fetch -o fetch -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
-        f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/write -o write -- "
+        f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/write -o write -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
-        "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/copyf -o copyf -- "
+        "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/copyf -o copyf -- "
         "python3 $REPO/bench.py --copy-calibration",
-        "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/copyw -o copyw -- "
+        "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/copyw -o copyw -- "
         "python3 $REPO/bench.py --copy-calibration",
         "```",
         "",
@@ -120,7 +121,34 @@ def summarize(args) -> None:
             json.dump(data, f, indent=1, sort_keys=True)
 
 
+def kernel_table(args) -> None:
+    """Per-kernel calls, total and average time of one traced command."""
+    stats = kernel_stats(args.trace)
+    rows = sorted(((c * a, k, c, a) for k, (c, a) in stats.items()), reverse=True)
+    total = sum(r[0] for r in rows)
+    lines = [f"# rocprofv3: {args.title}", "", "Command (run on the MI355X box from /tmp, REPO = the "
+             "repository root):", "", "```", args.command, "```", "",
+             f"Kernel time in the traced run: {total / 1e6:.2f} ms.", "",
+             "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
+    for tot, k, c, a in rows[:args.top]:
+        short = k if len(k) < 90 else k[:87] + "..."
+        lines.append(f"| `{short}` | {c} | {tot / 1e6:.2f} | {a / 1e3:.1f} | {tot / total:.1%} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main() -> None:
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "kernels":
+        ap = argparse.ArgumentParser(description=kernel_table.__doc__)
+        ap.add_argument("mode")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--command", required=True)
+        ap.add_argument("--top", type=int, default=12)
+        ap.add_argument("--out", required=True)
+        kernel_table(ap.parse_args())
+        return
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
@@ -129,7 +157,7 @@ def main() -> None:
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--copy-kernel", default="copyBuffer")
-    ap.add_argument("--kernel", default="gemm_kernel<false, false>")
+    ap.add_argument("--kernel", default="gemm_kernel<false, false, false, false>")
     ap.add_argument("--workload", default="square_n8192")
     ap.add_argument("--mnk", type=int, nargs=3, default=[8192, 8192, 8192])
     ap.add_argument("--kernel-hash", required=True)

@@ -357,6 +357,75 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
     }
 
 
+def run_serve_bench(args, dev) -> list[dict]:
+    """serve_lu: the request queue under Poisson arrivals, one JSON line per
+    arrival rate.  Each request is a new LU system (n log-uniform in [32, 2048],
+    nrhs in [1, 32]); its latency is completion minus submission on the queue's
+    own clock.  Payloads are converted to posit patterns before the clock
+    starts; requests of the same n share one system (B's first nrhs columns)."""
+    import threading
+    import torch
+    from paper_2401_14117_amd import posit32
+    from paper_2401_14117_amd import workloads as W
+    lines = []
+    payload = {}                                   # n -> (A, B with 32 columns)
+    for qps in args.qps:
+        t_arr, n, nrhs = W.serve_stream(qps, args.serve_seconds)
+        for k in n.tolist():
+            if k not in payload:
+                A, B = W.serve_system(k, 32, 7000)
+                Ap = posit32.from_f64(torch.from_numpy(A).to(dev)).cpu().numpy().view(np.uint32)
+                Bp = posit32.from_f64(torch.from_numpy(B).to(dev)).cpu().numpy().view(np.uint32)
+                payload[k] = (Ap, Bp)
+        q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=512)
+        # warm-up: one small and one large system
+        for k in (64, 1024):
+            A, B = W.serve_system(k, 2, 7001)
+            Ap = posit32.from_f64(torch.from_numpy(A).to(dev)).cpu().numpy().view(np.uint32)
+            Bp = posit32.from_f64(torch.from_numpy(B).to(dev)).cpu().numpy().view(np.uint32)
+            q.wait(q.submit(posit32.REQ_LU, Bp, Ap), 120.0)
+        tickets = [None] * len(n)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i in range(len(n)):
+                delay = t_arr[i] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                Ap, Bp = payload[int(n[i])]
+                tickets[i] = q.submit(posit32.REQ_LU, Bp[:, :int(nrhs[i])], Ap)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        outs = [q.wait(t, 600.0) for t in tickets]
+        st = q.stats()
+        q.close()
+        lat = np.array([o["done_s"] - o["submit_s"] for o in outs]) * 1e3
+        span = max(o["done_s"] for o in outs) - min(o["submit_s"] for o in outs)
+        bad = sum(1 for o in outs if o["status"] != 0 or o["info"] != 0)
+        small = n <= 512
+        lines.append({
+            "metric": "Posit32 served LU factor+solve solves/s (Poisson arrivals, p50/p99 latency)",
+            "value": round(len(n) / span, 1), "unit": "solves/s", "n_gpus": 1,
+            "steps": 1, "warmup": 2, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "posit32 (int32 VALU)",
+            "data": "synthetic",
+            "config": {"workload": "serve_lu", "qps": qps, "requests": int(len(n)),
+                       "seconds": args.serve_seconds, "n": "round(exp(U(ln 32, ln 2048)))",
+                       "nrhs": "1..32", "batch_max_n": 512,
+                       "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                       "p50_ms_small_n": round(float(np.percentile(lat[small], 50)), 2) if small.any() else None,
+                       "p99_ms_small_n": round(float(np.percentile(lat[small], 99)), 2) if small.any() else None,
+                       "mean_batch": round(st["systems_done"] / max(st["batches"], 1), 2),
+                       "failed": bad, "factor_gpops": round(
+                           float(np.sum(2.0 * n.astype(np.float64) ** 3 / 3)) / span / 1e9, 1)},
+            "roofline": None, "cpu_baseline": None,
+        })
+    return lines
+
+
 def to_device_patterns(mat, dev):
     """FP64 values -> Posit(32,2) patterns with the library's own conversion;
     the sprinkled special values are then set by index."""
@@ -415,12 +484,16 @@ def main() -> int:
     ap.add_argument("--workload", default="square_n8192",
                     help="square_nN | trailing_jJ | uniform_nN | normal_sigmaS_nN (Rgemm), "
                          "getrf_nN | potrf_nN (factor+solve), batch_lu | batch_chol (batched "
-                         "factor+solve), ew_OP_IR | ew_all (elementwise, OP in add/mul/div/sqrt, "
-                         "R in 0..4)")
+                         "factor+solve), serve_lu (request queue), ew_OP_IR | ew_all "
+                         "(elementwise, OP in add/mul/div/sqrt, R in 0..4)")
     ap.add_argument("--trans", default="nn", choices=["nn", "nt", "tn", "tt"],
                     help="Rgemm transposes op(A), op(B) (square workloads reuse the buffers)")
     ap.add_argument("--ew-n", type=int, default=1 << 26, help="elements of the elementwise workloads")
     ap.add_argument("--batch-count", type=int, default=20000, help="systems of the batched workloads")
+    ap.add_argument("--qps", type=float, nargs="+", default=[25.0, 50.0, 100.0, 150.0],
+                    help="arrival rates of the serving workload (requests per second)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of each arrival stream of the serving workload")
     ap.add_argument("--single-count", type=int, default=300,
                     help="sampled systems timed one at a time beside the batched workloads (0: skip)")
     ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
@@ -452,6 +525,10 @@ def main() -> int:
 
     if args.workload.startswith(("getrf_n", "potrf_n")):
         print(json.dumps(run_solve_bench(args.workload, args, dev)))
+        return 0
+    if args.workload == "serve_lu":
+        for line in run_serve_bench(args, dev):
+            print(json.dumps(line), flush=True)
         return 0
     if args.workload in ("batch_lu", "batch_chol"):
         print(json.dumps(run_batch_bench(args.workload, args, dev)))

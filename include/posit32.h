@@ -211,6 +211,86 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
                           const int32_t* nrhs, posit32_t* const* A, const int64_t* lda,
                           posit32_t* const* B, const int64_t* ldb, int32_t* info);
 
+/*
+ * Request queue (serving): many independent systems of different sizes,
+ * submitted one by one from host memory and solved with continuous batching
+ * on the device current at creation.  The queue owns one worker thread, two
+ * streams (compute and copy) and a device pool of cfg->device_bytes that holds
+ * every admitted system's A, B and pivots and every resident factorisation.
+ *
+ *  - Admission is in arrival order: a request waits at the head of the queue
+ *    until its footprint (4 n^2 + 4 n nrhs + 4 n bytes, each part rounded up
+ *    to 256) fits the pool.
+ *  - Whenever fewer than two batches are in flight, the worker launches every
+ *    admitted waiting request (up to cfg->max_batch) as one batch: systems with
+ *    n <= cfg->batch_max_n through the batched kernels, larger ones through
+ *    the single-matrix routines; host-to-device copies overlap the previous
+ *    batch's computation.
+ *  - Each system is factored and solved exactly as posit32_gesv_vbatched /
+ *    posit32_posv_vbatched (or the single-matrix calls) with block size
+ *    cfg->nb would do it: the solution is bit-identical however requests are
+ *    batched.
+ *  - keep = 1 keeps a successful factorisation resident; the handle comes
+ *    back in posit32_result.factor.  A later request with factor = handle
+ *    (same kind and n, A ignored) is solved with it without refactoring.
+ *    posit32_factor_release frees it once no request in flight uses it.
+ *
+ * posit32_queue_submit copies A and B; the caller may reuse them at once.
+ * posit32_queue_poll / posit32_queue_wait return 1 while the request is
+ * pending; once it has completed they fill *res, copy the n x nrhs solution
+ * into X (unless X is NULL), retire the ticket and return res->status: 0, or
+ * P32_E_NOMEM (the system can never fit the pool), or a P32_E_HIP code.  info
+ * is the factorisation's (as posit32_getrf / posit32_potrf); a factorisation
+ * with info > 0 is not solved and not kept (X is then the unsolved B).  Times
+ * are seconds on the host's monotonic clock since the queue was created.
+ * All calls are thread-safe.  Errors: -1 bad queue or cfg (device_bytes below
+ * 1 MiB, max_batch < 1, nb outside 1..256, batch_max_n < 0), -2 bad request,
+ * ticket or factor handle, P32_E_NOMEM from submit for a system larger than
+ * the pool.  posit32_queue_destroy finishes every submitted request first.
+ */
+#define P32_E_NOMEM (-4000)          /* below every P32_E_HIP code */
+enum { P32_REQ_LU = 0, P32_REQ_CHOL = 1 };
+
+typedef struct posit32_queue posit32_queue;
+
+typedef struct {
+  int64_t device_bytes;      /* device pool for admitted systems and resident factors */
+  int32_t max_batch;         /* most systems per batch */
+  int32_t nb;                /* block size of the factorisations */
+  int32_t batch_max_n;       /* largest n sent through the batched kernels */
+} posit32_queue_cfg;
+
+typedef struct {
+  int32_t kind;              /* P32_REQ_LU or P32_REQ_CHOL */
+  int32_t keep;              /* 1: keep the factorisation resident */
+  int64_t n, nrhs;           /* n >= 1, nrhs >= 1 */
+  const posit32_t* A;        /* host, n x n row-major (unused with a factor handle) */
+  const posit32_t* B;        /* host, n x nrhs row-major */
+  uint64_t factor;           /* 0, or a resident factorisation to solve with */
+} posit32_request;
+
+typedef struct {
+  int32_t status;            /* 1 pending, 0 done, < 0 error */
+  int32_t info;
+  uint64_t factor;           /* handle of the kept factorisation, else 0 */
+  double submit_s, start_s, done_s;
+} posit32_result;
+
+typedef struct {
+  int64_t pending, inflight_batches, batches, systems_done;
+  int64_t pool_bytes, pool_used, resident_factors;
+  int32_t error;             /* first runtime failure of the worker, else 0 */
+} posit32_queue_stats_t;
+
+int posit32_queue_create(const posit32_queue_cfg* cfg, posit32_queue** q);
+int posit32_queue_submit(posit32_queue* q, const posit32_request* req, uint64_t* ticket);
+int posit32_queue_poll(posit32_queue* q, uint64_t ticket, posit32_t* X, posit32_result* res);
+int posit32_queue_wait(posit32_queue* q, uint64_t ticket, double timeout_s, posit32_t* X,
+                       posit32_result* res);
+int posit32_factor_release(posit32_queue* q, uint64_t factor);
+int posit32_queue_stats(posit32_queue* q, posit32_queue_stats_t* stats);
+int posit32_queue_destroy(posit32_queue* q);
+
 #ifdef __cplusplus
 }
 #endif

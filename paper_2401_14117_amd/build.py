@@ -10,7 +10,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposit32.so")
-SOURCES = ["p32_gemm.hip", "p32_elementwise.hip", "p32_lapack.hip", "p32_batched.hip", "p32_api.cpp"]
+SOURCES = ["p32_gemm.hip", "p32_elementwise.hip", "p32_lapack.hip", "p32_batched.hip", "p32_server.hip",
+           "p32_api.cpp"]
 ARCH = "gfx950"
 
 
@@ -25,7 +26,7 @@ def flags() -> list[str]:
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # packed FP32 instructions are never wanted here (integer code)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
+            "-Wall", "-Wno-unused-result", "-pthread", "-I", os.path.join(HERE, "..", "include")]
 
 
 def build(verbose: bool = False, out: str | None = None, defines: list[str] | None = None) -> str:
@@ -54,7 +55,7 @@ def build(verbose: bool = False, out: str | None = None, defines: list[str] | No
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = lib + ".tmp"
-    r = subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs,
+    r = subprocess.run([cc, "-shared", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs,
                        capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

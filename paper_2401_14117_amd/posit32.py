@@ -26,9 +26,36 @@ OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_SQRT = range(5)
 
 _lib = None
 
+REQ_LU, REQ_CHOL = 0, 1
+E_NOMEM = -4000
+
 
 class Posit32Error(RuntimeError):
     pass
+
+
+class QueueCfg(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("nb", ctypes.c_int32), ("batch_max_n", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("keep", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("nrhs", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("factor", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("info", ctypes.c_int32), ("factor", ctypes.c_uint64),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+
+class QueueStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("inflight_batches", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("systems_done", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_int64), ("pool_used", ctypes.c_int64),
+                ("resident_factors", ctypes.c_int64), ("error", ctypes.c_int32)]
 
 
 def lib() -> ctypes.CDLL:
@@ -58,6 +85,17 @@ def lib() -> ctypes.CDLL:
     L.posit32_potrf_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
     L.posit32_potrs_vbatched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.posit32_posv_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_queue_create.argtypes = [ctypes.POINTER(QueueCfg), ctypes.POINTER(ctypes.c_void_p)]
+    L.posit32_queue_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.posit32_queue_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Result)]
+    L.posit32_queue_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, vp, ctypes.POINTER(Result)]
+    L.posit32_factor_release.argtypes = [vp, ctypes.c_uint64]
+    L.posit32_queue_stats.argtypes = [vp, ctypes.POINTER(QueueStats)]
+    L.posit32_queue_destroy.argtypes = [vp]
+    for f in (L.posit32_queue_create, L.posit32_queue_submit, L.posit32_queue_poll,
+              L.posit32_queue_wait, L.posit32_factor_release, L.posit32_queue_stats,
+              L.posit32_queue_destroy):
+        f.restype = i32
     for f in (L.posit32_from_f64, L.posit32_to_f64, L.posit32_elementwise, L.posit32_getrf,
               L.posit32_getrs, L.posit32_potrf, L.posit32_potrs, L.posit32_getrf_vbatched,
               L.posit32_getrs_vbatched, L.posit32_gesv_vbatched, L.posit32_potrf_vbatched,
@@ -308,3 +346,78 @@ class VBatch:
                                            _ptr(self.B), _ptr(self.ldb), _ptr(self.info)),
                "posit32_posv_vbatched")
         return self.info
+
+
+class Queue:
+    """Request queue of the library (posit32_queue_*): submit systems from host
+    memory (numpy uint32 patterns), collect their solutions later.  Solutions
+    are bit-identical to the batched and single-matrix calls."""
+
+    def __init__(self, device_bytes: int = 2 << 30, max_batch: int = 1024, nb: int = 256,
+                 batch_max_n: int = 512):
+        import numpy as np  # noqa: F401
+        cfg = QueueCfg(device_bytes, max_batch, nb, batch_max_n)
+        h = ctypes.c_void_p()
+        _check(lib().posit32_queue_create(ctypes.byref(cfg), ctypes.byref(h)), "posit32_queue_create")
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, kind: int, B, A=None, keep: bool = False, factor: int = 0) -> int:
+        """Queue one system; A (n x n) and B (n x nrhs or n) are numpy arrays of
+        posit patterns (copied at once).  Returns the ticket."""
+        import numpy as np
+        B2 = np.ascontiguousarray(B, dtype=np.uint32)
+        if B2.ndim == 1:
+            B2 = B2.reshape(-1, 1)
+        n, nrhs = B2.shape
+        A2 = None if A is None else np.ascontiguousarray(A, dtype=np.uint32)
+        if A2 is not None and A2.shape != (n, n):
+            raise ValueError("A must be n x n")
+        req = Request(kind, int(keep), n, nrhs,
+                      None if A2 is None else A2.ctypes.data, B2.ctypes.data, factor)
+        t = ctypes.c_uint64()
+        _check(lib().posit32_queue_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "posit32_queue_submit")
+        self._shapes[t.value] = (n, nrhs)
+        return t.value
+
+    def _collect(self, ticket: int, call):
+        import numpy as np
+        n, nrhs = self._shapes[ticket]
+        X = np.empty((n, nrhs), dtype=np.uint32)
+        res = Result()
+        rc = call(X.ctypes.data, ctypes.byref(res))
+        if rc == 1:
+            return None
+        if -1000 < rc < 0:                        # bad ticket or argument
+            _check(rc, "posit32_queue_poll/wait")
+        del self._shapes[ticket]
+        return {"X": X, "status": res.status, "info": res.info, "factor": res.factor,
+                "submit_s": res.submit_s, "start_s": res.start_s, "done_s": res.done_s}
+
+    def poll(self, ticket: int):
+        """The result dict once the request is done, else None."""
+        return self._collect(ticket, lambda x, r: lib().posit32_queue_poll(self._h, ticket, x, r))
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        return self._collect(ticket, lambda x, r: lib().posit32_queue_wait(self._h, ticket,
+                                                                              timeout_s, x, r))
+
+    def release(self, factor: int) -> None:
+        _check(lib().posit32_factor_release(self._h, factor), "posit32_factor_release")
+
+    def stats(self) -> dict:
+        st = QueueStats()
+        _check(lib().posit32_queue_stats(self._h, ctypes.byref(st)), "posit32_queue_stats")
+        return {f: getattr(st, f) for f, _ in QueueStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().posit32_queue_destroy(self._h), "posit32_queue_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

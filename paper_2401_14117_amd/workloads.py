@@ -187,3 +187,26 @@ def batch_matrices(kind: str, n: np.ndarray, nrhs: np.ndarray, seed: int = 6000,
         A = M if kind == "lu" else M @ M.T / k + np.eye(k)
         B = A @ np.ones((k, int(nrhs[i])))
         yield i, A, B
+
+
+def serve_stream(qps: float, duration_s: float, seed: int = 7000):
+    """Request stream of the serving workload: Poisson arrivals at rate qps
+    over duration_s (exponential gaps), each request n = round(exp(U(ln 32,
+    ln 2048))) and nrhs = integers(1, 32, inclusive).  Returns (arrival times,
+    n, nrhs)."""
+    rng = np.random.default_rng([seed, int(round(qps * 1000))])
+    count = max(1, int(rng.poisson(qps * duration_s)))
+    t = np.cumsum(rng.exponential(1.0 / qps, count))
+    n = np.round(np.exp(rng.uniform(np.log(32), np.log(2048), count))).astype(np.int64)
+    nrhs = rng.integers(1, 32, size=count, endpoint=True).astype(np.int64)
+    return t, n, nrhs
+
+
+def serve_system(n: int, nrhs: int, seed: int, kind: str = "lu"):
+    """Payload of one served request (FP64): LU entries uniform[-1, 1],
+    Cholesky M M^T / n + I; B uniform[-1, 1]; generator (seed, n, nrhs)."""
+    rng = np.random.default_rng([seed, n, nrhs])
+    M = rng.uniform(-1.0, 1.0, (n, n))
+    A = M if kind == "lu" else M @ M.T / n + np.eye(n)
+    B = rng.uniform(-1.0, 1.0, (n, nrhs))
+    return A, B

@@ -103,3 +103,20 @@ def test_vbatched_argument_errors(L):
     assert L.posit32_potrf_vbatched(None, 0, 0, 256, None, None, None, None) == 0
     assert L.posit32_gesv_vbatched(None, 0, 0, 256, None, None, None, None, None, None, None,
                                    None) == 0
+
+
+def test_queue_argument_errors(L):
+    # configuration and handle checks happen before any device call
+    from paper_2401_14117_amd.posit32 import QueueCfg, Request
+    import ctypes
+    h = ctypes.c_void_p()
+    for cfg in (QueueCfg(1 << 10, 16, 256, 512), QueueCfg(1 << 30, 0, 256, 512),
+                QueueCfg(1 << 30, 16, 0, 512), QueueCfg(1 << 30, 16, 300, 512),
+                QueueCfg(1 << 30, 16, 256, -1)):
+        assert L.posit32_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert L.posit32_queue_create(None, ctypes.byref(h)) == -1
+    t = ctypes.c_uint64()
+    assert L.posit32_queue_submit(None, ctypes.byref(Request()), ctypes.byref(t)) == -1
+    assert L.posit32_factor_release(None, 1) == -1
+    assert L.posit32_queue_destroy(None) == -1
+    assert L.posit32_strerror(-4000) == b"the system does not fit the queue's device pool"

@@ -145,8 +145,8 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  * All pointers are device memory; calls are stream-ordered and asynchronous
  * (info is written on the device).  posit32_getrf takes a stream-ordered
  * temporary of 8n bytes (hipMallocAsync) for its pivot search.
- * Errors: -2 n < 0; -3 nb outside [1, 256] (getrf/potrf) or nrhs < 0
- * (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
+ * Errors: -2 n < 0; -3 nb outside [1, 256] (getrf/potrf) or nrhs outside
+ * [0, 2^31 - 1] (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
  * pointer/leading-dimension arguments in order (-6, -7, ...).
  */
 int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,

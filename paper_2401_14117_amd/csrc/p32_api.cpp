@@ -80,7 +80,7 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
 int posit32_getrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
                   const int32_t* ipiv, posit32_t* B, int64_t ldb) {
   if (n < 0) return -2;
-  if (nrhs < 0) return -3;
+  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -3;   // one workgroup per right-hand side
   if (n > 0 && LU == nullptr) return -4;
   if (lda < (n > 1 ? n : 1)) return -5;
   if (n > 0 && ipiv == nullptr) return -6;
@@ -101,7 +101,7 @@ int posit32_potrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
 int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
                   posit32_t* B, int64_t ldb) {
   if (n < 0) return -2;
-  if (nrhs < 0) return -3;
+  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -3;
   if (n > 0 && L == nullptr) return -4;
   if (lda < (n > 1 ? n : 1)) return -5;
   if (n > 0 && nrhs > 0 && B == nullptr) return -6;

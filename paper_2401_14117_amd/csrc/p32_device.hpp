@@ -317,6 +317,19 @@ __device__ __forceinline__ int32_t round_lut(int32_t h2, uint2 p) {
   return (q & (int32_t)p.y) >> 2;
 }
 
+// The same parameters unpacked into one 16-byte entry: x = r, y = 2^(r-1) - 1,
+// z = ~(2^r - 1), so no shift is needed to separate them.
+__device__ __forceinline__ uint4 round_params4(int sc) {
+  const uint2 p = round_params(sc);
+  return make_uint4(p.x & 31u, p.x >> 5, p.y, 0u);
+}
+
+__device__ __forceinline__ int32_t round_lut4(int32_t h2, uint4 p) {
+  const int32_t lsb = (int32_t)__builtin_amdgcn_ubfe((uint32_t)h2, p.x, 1u);
+  const int32_t q = h2 + (int32_t)p.y + lsb;
+  return (q & (int32_t)p.z) >> 2;
+}
+
 // product of decoded operands given as a8 = s_a << 3 and b4 = s_b << 2:
 // |P| in [2^59, 2^61), normalised to a leading bit at 60.
 __device__ __forceinline__ win mul_core(int32_t a8, int32_t sca, int32_t b4, int32_t scb, int& c3) {

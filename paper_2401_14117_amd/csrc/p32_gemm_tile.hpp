@@ -22,7 +22,15 @@ namespace p32 {
 #define P32_GEMM_TN 2             // columns of C per thread
 #endif
 
-constexpr int TM = P32_GEMM_TM, TN = P32_GEMM_TN, NT = 256, BK = 16;
+#ifndef P32_GEMM_LUT4
+#define P32_GEMM_LUT4 1           // 16-byte rounding-table entries (no unpacking shift)
+#endif
+
+#ifndef P32_GEMM_BK
+#define P32_GEMM_BK 16            // k-tile depth staged per barrier pair
+#endif
+
+constexpr int TM = P32_GEMM_TM, TN = P32_GEMM_TN, NT = 256, BK = P32_GEMM_BK;
 constexpr int BM = 16 * TM, BN = 16 * TN;   // 16 x 16 threads per workgroup
 constexpr unsigned GROUP_M = 8;             // tile rows per group of the tile order
 constexpr int EB = 8192 + 128;           // exponent bias inside the kernel
@@ -95,30 +103,40 @@ __device__ __forceinline__ bool add_checked(win a, win b, win& out) {
 // The rounding parameters come from the LDS table; exponent differences use
 // saturating subtraction and the one test left covers cancellation (c3 < 0)
 // and alignments of 64 bits or more, which go to the exact path.
-__device__ __forceinline__ win mul_unchecked(int2 a, int2 b, const uint2* __restrict__ lut) {
+#if P32_GEMM_LUT4
+typedef uint4 lut_t;
+__device__ __forceinline__ lut_t make_lut_entry(int sc) { return round_params4(sc); }
+__device__ __forceinline__ int32_t round_entry(int32_t h2, lut_t p) { return round_lut4(h2, p); }
+#else
+typedef uint2 lut_t;
+__device__ __forceinline__ lut_t make_lut_entry(int sc) { return round_params(sc); }
+__device__ __forceinline__ int32_t round_entry(int32_t h2, lut_t p) { return round_lut(h2, p); }
+#endif
+
+__device__ __forceinline__ win mul_unchecked(int2 a, int2 b, const lut_t* __restrict__ lut) {
   const int64_t P = (int64_t)a.x * (int64_t)b.x;
   const int cnt = ffbh_i32((int32_t)(P >> 32));
   const int eb = a.y + b.y - cnt;
-  const uint2 rp = lut[eb & 255];
+  const lut_t rp = lut[eb & 255];
   win w;
-  w.h = round_lut(fold_sticky((uint64_t)P << ((cnt - 3) & 63)), rp);
+  w.h = round_entry(fold_sticky((uint64_t)P << ((cnt - 3) & 63)), rp);
   w.e = eb;
   return w;
 }
 
-__device__ __forceinline__ win add_unchecked(win a, win b, const uint2* __restrict__ lut,
+__device__ __forceinline__ win add_unchecked(win a, win b, const lut_t* __restrict__ lut,
                                              uint32_t& badbits) {
   const uint32_t db = __builtin_elementwise_sub_sat((uint32_t)a.e, (uint32_t)b.e);
   const uint32_t da = __builtin_elementwise_sub_sat((uint32_t)b.e, (uint32_t)a.e);
-  const int E = b.e + (int)db;                          // max(a.e, b.e)
+  const int E4 = b.e + (int)db + 4;                     // max(a.e, b.e) + 4
   const int64_t S = (((int64_t)a.h << 32) >> da) + (((int64_t)b.h << 32) >> db);
   const int cnt = ffbh_i32((int32_t)(S >> 32));
   const int c3 = cnt - 3;
   badbits |= da | db | (uint32_t)c3;                    // > 63 means: exact path
-  const int eb = E + 4 - cnt;
-  const uint2 rp = lut[eb & 255];
+  const int eb = E4 - cnt;
+  const lut_t rp = lut[eb & 255];
   win w;
-  w.h = round_lut(fold_sticky((uint64_t)S << (c3 & 63)), rp);
+  w.h = round_entry(fold_sticky((uint64_t)S << (c3 & 63)), rp);
   w.e = eb;
   return w;
 }
@@ -127,7 +145,7 @@ __device__ __forceinline__ win add_unchecked(win a, win b, const uint2* __restri
 // whole step on the exact path.
 template <bool CHECKED>
 __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restrict__ Arow,
-                                       const int2* __restrict__ Brow, const uint2* __restrict__ lut,
+                                       const int2* __restrict__ Brow, const lut_t* __restrict__ lut,
                                        int tx, int ty) {
   int2 a[TM], b[TN];
 #pragma unroll
@@ -179,7 +197,7 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
 struct TileLds {
   int2 As[BK][BM];   // (s << 3, scale + EB + 4) of op(A)(i0 + i, p0 + p)
   int2 Bs[BK][BN];   // (s << 2, scale) of op(B)(p0 + p, j0 + j)
-  uint2 lut[256];    // rounding parameters of scales -128..127
+  lut_t lut[256];    // rounding parameters of scales -128..127
   int rowNaR[BM], colNaR[BN];
 };
 
@@ -200,7 +218,7 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
   __syncthreads();                                // LDS of a previous tile no longer in use
   if (tid < BM) rowNaR[tid] = 0;
   if (tid < BN) colNaR[tid] = 0;
-  lut[tid] = round_params(tid - 128);   // NT == 256 entries
+  lut[tid] = make_lut_entry(tid - 128);   // NT == 256 entries
 
   win acc[TM][TN];
   uint32_t cnar = 0;            // CHAIN: bit i*TN+j set when C_ij starts as NaR

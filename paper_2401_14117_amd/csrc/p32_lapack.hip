@@ -265,26 +265,44 @@ __global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, i
 }
 
 // U12 = L11^-1 A12 (L11 unit lower, jb x jb at A[j][j]); one wave per column
-// of A12; lane t holds rows j + t + 64 u of the column
+// of A12, four columns per workgroup; lane t holds rows j + t + 64 u of its
+// column.  L11 is staged in LDS kTrsmCols columns at a time (shared by the
+// workgroup's four waves), so the dependent chain of column steps reads its
+// coefficients from LDS.
+constexpr int kTrsmCols = 32;
+
 __global__ void __launch_bounds__(256)
 trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb) {
+  __shared__ uint32_t Ls[kMaxNB][kTrsmCols + 1];
   const int lane = threadIdx.x & 63;
   const int64_t q = j + jb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= n) return;
+  const bool active = q < n;                      // every wave still stages and syncs
   uint32_t v[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int64_t r = lane + 64 * u;
-    v[u] = r < jb ? A[(j + r) * lda + q] : 0u;
+    v[u] = active && r < jb ? A[(j + r) * lda + q] : 0u;
   }
-  for (int c = 0; c < jb; ++c) {
-    const uint32_t bc = __shfl(pick4(v, c >> 6), c & 63);   // final value of row c
+  for (int c0 = 0; c0 < jb; c0 += kTrsmCols) {
+    const int w = (int)min((int64_t)kTrsmCols, jb - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < jb * w; idx += 256) {
+      const int r = idx / w, cl = idx - r * w;
+      Ls[r][cl] = A[(j + r) * lda + j + c0 + cl];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int cl = 0; cl < w; ++cl) {
+      const int c = c0 + cl;
+      const uint32_t bc = __shfl(pick4(v, c >> 6), c & 63);   // final value of row c
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = lane + 64 * u;
-      if (r > c && r < jb) v[u] = p_fms(v[u], A[(j + r) * lda + j + c], bc);
+      for (int u = 0; u < 4; ++u) {
+        const int r = lane + 64 * u;
+        if (r > c && r < jb) v[u] = p_fms(v[u], Ls[r][cl], bc);
+      }
     }
   }
+  if (!active) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int64_t r = lane + 64 * u;
@@ -358,42 +376,39 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
     for (int q = t & 63; q <= i; q += 64) G[i * lda + q] = D[tri_off(i) + q];
 }
 
-// L21 = A21 L11^-T: one wave per row of A21; lane t holds columns t + 64 u.
-// Column by column: x_c = A[r][c] / L[c][c] is final once the updates from
-// columns < c are in, then columns c' > c get A[r][c'] - rnd(x_c * L[c'][c]).
+// L21 = A21 L11^-T for the rows [r_begin, r_end) against the jb x jb triangle
+// at A[j][j] (jb <= kCholTrsmMax): one wave per row, lane t holds column
+// j + t.  Column by column: x_c = A[r][c] / L[c][c] is final once the updates
+// from columns < c are in, then columns c' > c get A[r][c'] - rnd(x_c *
+// L[c'][c]).  The triangle is staged in LDS once per workgroup (four rows).
+constexpr int kCholTrsmMax = 64;
+
 __global__ void __launch_bounds__(256)
 trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t r_end, int64_t j,
                  int64_t jb, const int32_t* __restrict__ info) {
+  __shared__ uint32_t Ls[kCholTrsmMax][kCholTrsmMax + 1];
   if (*info != 0) return;
   const int lane = threadIdx.x & 63;
+  const int w = (int)jb;
+  for (int idx = threadIdx.x; idx < w * w; idx += 256) {
+    const int cc = idx / w, c = idx - cc * w;
+    if (c <= cc) Ls[cc][c] = A[(j + cc) * lda + j + c];
+  }
+  __syncthreads();
   const int64_t r = r_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= r_end) return;
   uint32_t* row = A + r * lda + j;
-  const uint32_t* L = A + j * lda + j;
-  uint32_t v[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = lane + 64 * u;
-    v[u] = c < jb ? row[c] : 0u;
-  }
-  for (int c = 0; c < jb; ++c) {
+  uint32_t v = lane < w ? row[lane] : 0u;
+  for (int c = 0; c < w; ++c) {
     uint32_t xc = 0u;
-    if ((c & 63) == lane) {
-      xc = p_div(pick4(v, c >> 6), L[c * lda + c]);
-      put4(v, c >> 6, xc);
+    if (lane == c) {
+      xc = p_div(v, Ls[c][c]);
+      v = xc;
     }
-    xc = __shfl(xc, c & 63);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int cc = lane + 64 * u;
-      if (cc > c && cc < jb) v[u] = p_fms(v[u], xc, L[cc * lda + c]);
-    }
+    xc = __shfl(xc, c);
+    if (lane > c && lane < w) v = p_fms(v, xc, Ls[lane][c]);
   }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = lane + 64 * u;
-    if (c < jb) row[c] = v[u];
-  }
+  if (lane < w) row[lane] = v;
 }
 
 // ---- triangular solves -----------------------------------------------------
@@ -406,32 +421,32 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
   return kind == 3 ? M[c * lda + r] : M[r * lda + c];
 }
 
-// Diagonal block [s, s+bs) of the solve for the right-hand sides
-// [q0, q0+kRhsChunk) (one workgroup per chunk).  Thread r owns row s+r; the
-// block's unknowns live in LDS and the coefficients are staged in LDS 32
-// columns at a time.  Per column c (in solve order): the non-unit kinds divide
-// x[c] by the diagonal, then every later row r gets x[r] - rnd(T(r,c) x[c]).
+// Diagonal block [s, s+bs) of the solve for one right-hand side q (one
+// workgroup per right-hand side).  Thread r owns row s + r in a register; the
+// coefficients are staged in LDS kCoefCols columns at a time.  Per column c
+// (in solve order) the owner of row c, whose value is final once its own last
+// update is in, divides it by the diagonal (non-unit kinds) and publishes it
+// through LDS; after one barrier every later row r gets
+// x[r] - rnd(T(r,c) x[c]).  The published value is double-buffered by column
+// parity, so one barrier per column suffices.
 constexpr int kTrsvBlock = 256;
-constexpr int kRhsChunk = 4;
 constexpr int kCoefCols = 32;
 
 __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
                  int64_t nrhs, int64_t s, int bs, int kind) {
-  __shared__ uint32_t xs[kTrsvBlock][kRhsChunk];
   __shared__ uint32_t coef[kTrsvBlock][kCoefCols + 1];
   __shared__ uint32_t diag[kCoefCols];
+  __shared__ uint32_t xc_sh[2];
   const bool forward = kind == 0 || kind == 2;
   const bool unit = kind == 0;
   const int t = threadIdx.x;
-  const int64_t q0 = (int64_t)blockIdx.x * kRhsChunk;
-  const int nq = (int)min((int64_t)kRhsChunk, nrhs - q0);
-  if (t < bs)
-    for (int u = 0; u < nq; ++u) xs[t][u] = B[(s + t) * ldb + q0 + u];
+  const int64_t q = blockIdx.x;
+  uint32_t x = t < bs ? B[(s + t) * ldb + q] : 0u;
+  int parity = 0;
   for (int step0 = 0; step0 < bs; step0 += kCoefCols) {
     const int steps = min(kCoefCols, bs - step0);
     __syncthreads();
-    // stage T(r, c) for the next columns of the solve order, c = col(step)
     for (int idx = t; idx < bs * steps; idx += kTrsvBlock) {
       int r, u;
       if (kind == 3) { u = idx / bs; r = idx - u * bs; }   // row c of M is contiguous in r
@@ -445,22 +460,19 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
         diag[u] = M[c * lda + c];
       }
     __syncthreads();
-    for (int u = 0; u < steps; ++u) {
+    for (int u = 0; u < steps; ++u, parity ^= 1) {
       const int cl = forward ? step0 + u : bs - 1 - step0 - u;   // local column
-      if (!unit) {
-        if (t < nq) xs[cl][t] = p_div(xs[cl][t], diag[u]);
-        __syncthreads();
-      }
-      const bool below = forward ? t > cl : t < cl;
-      if (t < bs && below) {
-        const uint32_t m = coef[t][u];
-        for (int v = 0; v < nq; ++v) xs[t][v] = p_fms(xs[t][v], m, xs[cl][v]);
+      if (t == cl) {
+        if (!unit) x = p_div(x, diag[u]);
+        xc_sh[parity] = x;
       }
       __syncthreads();
+      const uint32_t xc = xc_sh[parity];
+      const bool below = forward ? t > cl : t < cl;
+      if (t < bs && below) x = p_fms(x, coef[t][u], xc);
     }
   }
-  if (t < bs)
-    for (int u = 0; u < nq; ++u) B[(s + t) * ldb + q0 + u] = xs[t][u];
+  if (t < bs) B[(s + t) * ldb + q] = x;
 }
 
 // rows outside the diagonal block [s, s+bs) get that block's columns, in
@@ -505,8 +517,8 @@ static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t s0 = forward ? b * bsz : (nblk - 1 - b) * bsz;
     const int64_t bs = s0 + bsz < n ? bsz : n - s0;
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3((unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk)),
-                       dim3(kTrsvBlock), 0, s, M, lda, B, ldb, nrhs, s0, (int)bs, kind);
+    hipLaunchKernelGGL(trsv_diag_kernel, dim3((unsigned)nrhs), dim3(kTrsvBlock), 0, s, M, lda, B, ldb,
+                       nrhs, s0, (int)bs, kind);
     const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? n : s0;
     const int64_t cnt = (r1 - r0) * nrhs;
     if (cnt > 0)
@@ -605,69 +617,74 @@ int launch_getrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* LU, int
   return trsv(s, LU, lda, n, B, ldb, nrhs, 1);
 }
 
-// lower triangle of the jb x jb block at A[j][j] -> dst (row stride kMaxNB)
-__global__ void save_lower_kernel(const uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb,
-                                  uint32_t* __restrict__ dst, const int32_t* __restrict__ info) {
-  if (*info != 0) return;
-  const int i = blockIdx.x;
-  for (int q = threadIdx.x; q <= i && q < jb; q += blockDim.x)
-    dst[i * kMaxNB + q] = A[(j + i) * lda + j + q];
+// Rows [j, n) of the block column [j, j+jb) -> dst (row stride kMaxNB):
+// inside the diagonal block only its lower triangle, below it whole rows.
+// restore: dst -> A for the rows below the block, and only when the block's
+// factorisation failed (info in [j+1, j+jb]).
+__global__ void save_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int64_t n,
+                                  uint32_t* __restrict__ dst, const int32_t* __restrict__ info,
+                                  int restore) {
+  const int32_t f = *info;
+  if (restore ? (f < j + 1 || f > j + jb) : f != 0) return;
+  const int64_t i = blockIdx.x;                  // row j + i
+  if (restore && i < jb) return;                 // the block itself is refactored from dst
+  const int w = i < jb ? (int)i + 1 : jb;
+  for (int q = threadIdx.x; q < w; q += blockDim.x) {
+    if (restore) A[(j + i) * lda + j + q] = dst[i * kMaxNB + q];
+    else dst[i * kMaxNB + q] = A[(j + i) * lda + j + q];
+  }
 }
 
 constexpr int64_t kCholSub = 32;     // columns per sub-block of a diagonal block
+static_assert(kCholSub <= kCholTrsmMax, "trsm_chol_kernel stages at most kCholTrsmMax columns");
 
 // Rpotrf.  Each diagonal block [j, j+jb) is factored kCholSub columns at a
-// time: the sub-block's own columns by potf2_kernel, the block's rows below
-// it by trsm_chol_kernel, and the rest of the block's lower triangle by one
-// fused-update chain over the sub-block's columns.  Every element receives
-// exactly the updates, divisions and square root of the unblocked order, in
-// the same sequence.  If a diagonal fails, the partial state of the
-// sub-blocked schedule differs from the unblocked one, so the block is
-// restored from a copy taken before it started and refactored unblocked,
-// which stops at the same column with the state the unblocked order leaves.
-// L21 = A21 L11^-T is then computed with the same sub-blocks (solve against
-// the sub-block's triangle, then a chain update of the later columns).
+// time, together with the rows below it: the sub-block's own columns by
+// potf2_kernel, every row below the sub-block (the rest of the block and
+// L21) by trsm_chol_kernel, and the lower triangle of the rest of the block
+// plus the L21 rows by one fused-update chain over the sub-block's columns.
+// Every element receives exactly the updates, divisions and square root of
+// the unblocked order (the diagonal block unblocked, then L21 row by row), in
+// the same sequence.  If a diagonal fails, that order stops inside the
+// diagonal block and leaves L21 untouched, so the rows [j, n) of the block
+// column are restored from a copy taken before the block started and the
+// block is refactored unblocked, which stops at the same column with the
+// state the unblocked order leaves.
 int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
   if (n == 0) return launch_status();
   uint32_t* saved = nullptr;
-  hipError_t e = hipMallocAsync((void**)&saved, (size_t)kMaxNB * kMaxNB * sizeof(uint32_t), s);
+  hipError_t e = hipMallocAsync((void**)&saved, (size_t)n * kMaxNB * sizeof(uint32_t), s);
   if (e != hipSuccess) return -1000 - (int)e;
   int rc = launch_status();
   for (int64_t j = 0; j < n && rc == 0; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;
-    hipLaunchKernelGGL(save_lower_kernel, dim3((unsigned)jb), dim3(256), 0, s, A, lda, j, (int)jb, saved,
-                       info);
-    for (int64_t c0 = j; c0 < j + jb && rc == 0; c0 += kCholSub) {
-      const int64_t sb = kCholSub < j + jb - c0 ? kCholSub : j + jb - c0;
+    const int64_t je = j + jb;
+    hipLaunchKernelGGL(save_panel_kernel, dim3((unsigned)(n - j)), dim3(256), 0, s, A, lda, j, (int)jb, n,
+                       saved, info, 0);
+    for (int64_t c0 = j; c0 < je && rc == 0; c0 += kCholSub) {
+      const int64_t sb = kCholSub < je - c0 ? kCholSub : je - c0;
       hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kPotf2Threads), 0, s, A, lda, c0, (int)sb, info,
                          (const uint32_t*)nullptr);
-      const int64_t r1 = c0 + sb, rin = j + jb - r1;
-      if (rin > 0) {
-        hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((rin + 3) / 4)), dim3(256), 0, s, A, lda, r1,
-                           j + jb, c0, sb, info);
-        rc = launch_fms_chain(s, 1, rin, rin, sb, A + r1 * lda + c0, lda, A + r1 * lda + c0, lda,
-                              A + r1 * lda + r1, lda, true, info);
+      const int64_t r1 = c0 + sb, below = n - r1;
+      if (below > 0) {
+        hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((below + 3) / 4)), dim3(256), 0, s, A, lda,
+                           r1, n, c0, sb, info);
+        // lower triangle of the rest of the block; every column of it for the
+        // rows below the block
+        if (je > r1)
+          rc = launch_fms_chain(s, 1, below, je - r1, sb, A + r1 * lda + c0, lda, A + r1 * lda + c0, lda,
+                                A + r1 * lda + r1, lda, true, info);
       }
     }
+    hipLaunchKernelGGL(save_panel_kernel, dim3((unsigned)(n - j)), dim3(256), 0, s, A, lda, j, (int)jb, n,
+                       saved, info, 1);
     hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kPotf2Threads), 0, s, A, lda, j, (int)jb, info,
                        (const uint32_t*)saved);
-    const int64_t rest = n - j - jb;
-    if (rest > 0 && rc == 0) {
-      const int64_t r0 = j + jb;
-      for (int64_t c0 = j; c0 < j + jb && rc == 0; c0 += kCholSub) {
-        const int64_t sb = kCholSub < j + jb - c0 ? kCholSub : j + jb - c0;
-        hipLaunchKernelGGL(trsm_chol_kernel, dim3((unsigned)((rest + 3) / 4)), dim3(256), 0, s, A, lda, r0,
-                           n, c0, sb, info);
-        const int64_t later = j + jb - (c0 + sb);
-        if (later > 0)
-          rc = launch_fms_chain(s, 1, rest, later, sb, A + r0 * lda + c0, lda, A + (c0 + sb) * lda + c0,
-                                lda, A + r0 * lda + c0 + sb, lda, false, info);
-      }
-      if (rc == 0)
-        rc = launch_gemm_ex(s, 0, 1, rest, rest, jb, kMinusOne, A + r0 * lda + j, lda, A + r0 * lda + j,
-                            lda, kOne, A + r0 * lda + r0, lda, true, info);
-    }
+    const int64_t rest = n - je;
+    if (rest > 0 && rc == 0)
+      rc = launch_gemm_ex(s, 0, 1, rest, rest, jb, kMinusOne, A + je * lda + j, lda, A + je * lda + j, lda,
+                          kOne, A + je * lda + je, lda, true, info);
     if (rc == 0) rc = launch_status();
   }
   e = hipFreeAsync(saved, s);

@@ -123,7 +123,8 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  *   Then the interchanges go to the other columns; U12 = L11^-1 A12 column
  *   by column (ascending c); A22 = Rgemm(alpha = -1, beta = 1, L21, U12).
  *   ipiv: device int32[n], 0-based (row c was swapped with row ipiv[c]).
- *   info: device int32[1], 0 or the 1-based column of the first zero pivot.
+ *   info: device int32[1], 0 or the 1-based column of the first zero pivot
+ *   (-1: see below).
  * posit32_getrs -- solve A X = B with the output of posit32_getrf; B is n x
  *   nrhs (ldb >= nrhs), overwritten by X.  Interchanges in order; forward
  *   L (unit): for c ascending, rows r > c get B[r] - rnd(L[r][c]*B[c]);
@@ -143,10 +144,16 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  *   B[c] = B[c] / L[c][c], rows above get B[r] - rnd(L[c][r]*B[c])).
  *
  * All pointers are device memory; calls are stream-ordered and asynchronous
- * (info is written on the device).  posit32_getrf takes a stream-ordered
- * temporary of 8n bytes (hipMallocAsync) for its pivot search.
- * Errors: -2 n < 0; -3 nb outside [1, 256] (getrf/potrf) or nrhs outside
- * [0, 2^31 - 1] (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
+ * (info is written on the device).  posit32_getrf factors each panel in one
+ * cooperative launch whose workgroups exchange pivot candidates through a
+ * stream-ordered temporary (hipMallocAsync, about 0.5 MB); should that
+ * exchange ever wait longer than its bound (a device fault, never a property
+ * of the input), info is set to -1.  posit32_potrf takes a stream-ordered
+ * temporary of 1 KiB per row (the block column it restores after a failed
+ * diagonal).
+ * Errors: -2 n < 0 (getrf: also n > 2^24 - 2, pivot rows are carried in 24
+ * bits); -3 nb outside [1, 256] (getrf/potrf) or nrhs outside [0, 2^31 - 1]
+ * (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
  * pointer/leading-dimension arguments in order (-6, -7, ...).
  */
 int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,

@@ -40,10 +40,8 @@ def build(verbose: bool = False, out: str | None = None, defines: list[str] | No
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        # every translation unit, host-only ones included, is built for gfx950 only
         cmd = [cc] + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [cc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I",
-                   os.path.join(HERE, "..", "include"), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)

@@ -3,7 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/posit32.h"
+#include "posit32.h"
 #include "p32_launch.hpp"
 
 extern "C" {

@@ -423,6 +423,15 @@ __device__ inline win add_win(win a, win b) {
   return win_of(add_general(a, b));
 }
 
+// acc - rnd(b * c) rounded, with acc in window form (exactly a posit value)
+// and b, c decoded, none of them NaR: a running value kept decoded across a
+// chain of fused updates, encoded only when it is published
+__device__ inline win fms_win(win acc, dec b, dec c) {
+  win pr = mul_win(b, c);
+  pr.h = -pr.h;
+  return add_win(acc, pr);
+}
+
 // rnd(a - rnd(b * c)), with b and c given as patterns and already decoded
 __device__ inline uint32_t p_fms_pre(uint32_t a, uint32_t b, dec db, uint32_t c, dec dc) {
   if (a == kNaR || b == kNaR || c == kNaR) return kNaR;

@@ -7,21 +7,22 @@
 // every element receives its updates in the stated order, so the results are
 // bit-identical to a plain sequential run of that schedule:
 //
-//  Rgetrf, per panel [j, j+jb):
-//    for each column c: pivot search (argmax |A[i][c]| in posit order over
-//    i >= c, ties to the smallest row; a 64-bit atomic max per wave), row
-//    swap inside the panel, scaling of the column by the pivot, rank-1
-//    update of the panel's remaining columns -- fused with the pivot search
-//    of the next column;
-//    interchanges applied to the other columns; U12 = L11^-1 A12 (one wave
-//    per column of A12); trailing update A22 = Rgemm(-1, 1, L21, U12).
-//  Rpotrf, per diagonal block: unblocked Cholesky of the block in one
-//    workgroup; L21 = A21 L11^-T (one wave per row of A21); lower triangle of
-//    A22 = Rgemm(-1, 1, L21, L21^T).  A failed diagonal sets info and every
-//    later kernel of the call sees it and does nothing.
+//  Rgetrf, per panel [j, j+jb): one cooperative launch factors the panel
+//    column by column (pivot search over all its rows, swap, scaling, rank-1
+//    update of the panel's remaining columns), the rows spread over the
+//    workgroups and the pivot candidates exchanged through per-workgroup
+//    slots; then the interchanges go to the other columns, U12 = L11^-1 A12
+//    (one wave per column of A12) and A22 = Rgemm(-1, 1, L21, U12).
+//  Rpotrf, per diagonal block, kCholSub columns at a time: the sub-block's
+//    unblocked Cholesky in one workgroup, every row below it solved against
+//    its triangle (one wave per row), and a fused-update chain over its
+//    columns for the rest of the block and the rows below it; then the lower
+//    triangle of A22 = Rgemm(-1, 1, L21, L21^T).  A failed diagonal sets
+//    info, the block column is restored and refactored unblocked, and every
+//    later kernel of the call sees info and does nothing.
 //  Rgetrs / Rpotrs: blocked triangular solves -- a diagonal block solved by
-//    one workgroup, then the rows outside it updated in parallel, applying
-//    the block's columns in the stated order.
+//    one workgroup per right-hand side, then the rows outside it updated in
+//    parallel, applying the block's columns in the stated order.
 #include <hip/hip_runtime.h>
 
 #include "p32_device.hpp"
@@ -89,29 +90,36 @@ __device__ __forceinline__ int64_t slot_row(unsigned long long v) {
 // Factorisation of the panel A[j:n, j:j+jb] by one cooperative launch (all
 // workgroups resident).  Workgroup w owns the R consecutive rows starting at
 // j + w R (in LDS when they fit, else in place in A).  Per column c:
-//   1. every workgroup publishes its best pivot candidate for column c: a
-//      copy of the whole panel row, then its slot; the owner of row c also
-//      publishes a copy of row c;
+//   1. every workgroup has published its best pivot candidate for column c (a
+//      copy of the whole panel row, then its slot), and the owner of row c a
+//      copy of row c;
 //   2. every workgroup waits until all slots carry the tag of column c (this
 //      is the only grid-wide synchronisation) and takes the largest;
 //   3. the owners of rows c and p swap them from the published copies, and
-//      each workgroup scales column c and applies the rank-1 update to its
-//      rows below c.
-// Other workgroups' rows are only read from the published copies; copies and
-// slots are double-buffered by the parity of c (a workgroup can be at most
-// one column ahead of any other).  A wait that exceeds kPollLimit rounds
-// gives up: info is set to -1 and the workgroup exits, so no wave can wait
-// forever.  Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb].
+//      each workgroup scales column c of its rows below c;
+//   4. look-ahead: it applies column c's rank-1 update first to column c+1
+//      (all its rows below c), picks its candidate for column c+1, completes
+//      the update of the two rows it is about to publish (the candidate and
+//      row c+1), publishes them (step 1 of column c+1), and only then applies
+//      the update to the rest of its rows, while the other workgroups are
+//      still publishing.
+// Every element still receives column c's update before column c+1's, and
+// the pivot search of column c+1 sees column c+1 fully updated, so the order
+// of operations is that of the unblocked factorisation.  Other workgroups'
+// rows are only read from the published copies; copies and slots are
+// double-buffered by the parity of c (a workgroup can be at most one column
+// ahead of any other).  A wait that exceeds kPollLimit rounds gives up: info
+// is set to -1 and the workgroup exits, so no wave can wait forever.
+// Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb].
 template <bool LDS>
 __global__ void __launch_bounds__(kPanelThreads)
 lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int jb, int R,
                 unsigned long long* __restrict__ slot, uint32_t* __restrict__ crow,
                 uint32_t* __restrict__ rowc, int32_t* __restrict__ ipiv, int32_t* __restrict__ info) {
   __shared__ uint32_t tile[LDS ? kPanelLds : 1];
-  __shared__ uint32_t urow[kMaxNB], orow[kMaxNB];
+  __shared__ uint32_t urow[kMaxNB];
   __shared__ dec udec[kMaxNB];
-  __shared__ unsigned long long red[kPanelThreads / 64];
-  __shared__ unsigned long long sbest;
+  __shared__ unsigned long long red[2][kPanelThreads / 64];
 
   const int t = threadIdx.x;
   const unsigned G = gridDim.x;
@@ -120,6 +128,7 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
   const int nr = (int)min((int64_t)R, n - r0);   // >= 1 by the host's choice of G
   uint32_t* T = LDS ? tile : A + r0 * lda + j;
   const int64_t ts = LDS ? jb : lda;              // row stride of T
+  int rpar = 0;                                   // parity of the reduction buffer
 
   if (LDS) {
     for (int idx = t; idx < nr * jb; idx += kPanelThreads) {
@@ -130,33 +139,37 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
   }
 
   // largest value over the threads of the workgroup, returned to all of them
+  // (one barrier; the buffer alternates so the next call cannot overwrite it
+  // while it is still being read)
   auto block_max = [&](unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) {
       const unsigned long long o = __shfl_xor(v, off);
       v = o > v ? o : v;
     }
-    if ((t & 63) == 0) red[t >> 6] = v;
+    if ((t & 63) == 0) red[rpar][t >> 6] = v;
     __syncthreads();
-    if (t == 0) {
-      unsigned long long b = red[0];
-      for (int i = 1; i < kPanelThreads / 64; ++i) b = red[i] > b ? red[i] : b;
-      sbest = b;
-    }
-    __syncthreads();
-    return sbest;
+    unsigned long long b = red[rpar][0];
+    for (int i = 1; i < kPanelThreads / 64; ++i) b = red[rpar][i] > b ? red[rpar][i] : b;
+    rpar ^= 1;
+    return b;
   };
 
-  // step 1 for column c
-  auto publish = [&](int64_t c) {
+  // this workgroup's candidate for column c (rows >= c, column c up to date)
+  auto candidate = [&](int64_t c) {
     const int cl = (int)(c - j);
-    const int par = (int)(c & 1);
     unsigned long long best = 0ull;
     for (int rr = t; rr < nr; rr += kPanelThreads)
       if (r0 + rr >= c) {
         const unsigned long long v = pivot_slot(T[rr * ts + cl], r0 + rr, c);
         best = v > best ? v : best;
       }
-    best = block_max(best);
+    return block_max(best);
+  };
+
+  // step 1 for column c: copies of the candidate row and of row c (both up
+  // to date in every column), then the slot
+  auto publish = [&](int64_t c, unsigned long long best) {
+    const int par = (int)(c & 1);
     if ((best >> 8) != 0ull) {
       const int rr = (int)(slot_row(best) - r0);
       uint32_t* dst = crow + ((size_t)par * G + w) * jb;
@@ -194,10 +207,24 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     return block_max(mine);
   };
 
+  // T[rr][q] -= rnd(T[rr][cl] * u_q) (column cl's rank-1 update) for the rows
+  // [ra, rb) except skip1 and skip2, and the columns [qa, qb)
+  auto update = [&](int cl, int ra, int rb, int qa, int qb, int skip1, int skip2) {
+    const int wq = qb - qa;
+    const int cnt = rb > ra && wq > 0 ? (rb - ra) * wq : 0;
+    for (int idx = t; idx < cnt; idx += kPanelThreads) {
+      const int dr = idx / wq;
+      const int rr = ra + dr, q = qa + (idx - dr * wq);
+      if (rr == skip1 || rr == skip2) continue;
+      const uint32_t l = T[rr * ts + cl];
+      T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+    }
+  };
+
+  publish(j, candidate(j));
   for (int cl = 0; cl < jb; ++cl) {
     const int64_t c = j + cl;
     const int par = (int)(c & 1);
-    publish(c);
     const unsigned long long best = await(c);
     if (best == 0ull) {
       if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -208,11 +235,13 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     const unsigned wp = (unsigned)((p - j) / R);
     const bool own_c = c >= r0 && c < r0 + nr;
     const bool own_p = p != c && p >= r0 && p < r0 + nr;
+    // the pivot row (published copy of row p) becomes row c; row c's copy goes to row p
     for (int q = t; q < jb; q += kPanelThreads) {
       const uint32_t u = read_u32(crow + ((size_t)par * G + wp) * jb + q);
       urow[q] = u;
       udec[q] = decode(u);
-      if (own_p) orow[q] = read_u32(rowc + (size_t)par * jb + q);
+      if (own_c) T[(c - r0) * ts + q] = u;
+      if (own_p) T[(p - r0) * ts + q] = read_u32(rowc + (size_t)par * jb + q);
     }
     __syncthreads();
     const uint32_t piv = urow[cl];
@@ -220,24 +249,35 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
       ipiv[c] = (int32_t)p;
       if (piv == 0u && *info == 0) *info = (int32_t)(c + 1);
     }
-    for (int q = t; q < jb; q += kPanelThreads) {
-      if (own_c) T[(c - r0) * ts + q] = urow[q];
-      if (own_p) T[(p - r0) * ts + q] = orow[q];
-    }
-    __syncthreads();
-    // rows below c: scale column c, then the rank-1 update right of it
+    // rows below c: scale column c
     const int rs = (int)max((int64_t)0, c + 1 - r0);
     if (piv != 0u)
       for (int rr = rs + t; rr < nr; rr += kPanelThreads) T[rr * ts + cl] = p_div(T[rr * ts + cl], piv);
     __syncthreads();
-    const int wq = jb - cl - 1;
-    const int cnt = nr > rs ? (nr - rs) * wq : 0;
-    for (int idx = t; idx < cnt; idx += kPanelThreads) {
-      const int dr = idx / wq;
-      const int rr = rs + dr, q = cl + 1 + (idx - dr * wq);
-      const uint32_t l = T[rr * ts + cl];
-      T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+    if (cl + 1 == jb) break;
+    const int64_t c1 = c + 1;
+    // look-ahead: column c+1 of every row below c, then the candidate for it
+    update(cl, rs, nr, cl + 1, cl + 2, -1, -1);
+    __syncthreads();
+    const unsigned long long nbest = candidate(c1);
+    // complete the rows about to be published: the candidate and row c+1
+    const int rw = (nbest >> 8) != 0ull ? (int)(slot_row(nbest) - r0) : -1;
+    const int rc1 = c1 >= r0 && c1 < r0 + nr ? (int)(c1 - r0) : -1;
+    {
+      const int wq = jb - cl - 2;
+      const int rows = (rw >= 0) + (rc1 >= 0 && rc1 != rw);
+      for (int idx = t; idx < rows * wq; idx += kPanelThreads) {
+        const int k = idx / wq;
+        const int rr = (k == 0 && rw >= 0) ? rw : rc1;
+        const int q = cl + 2 + (idx - k * wq);
+        const uint32_t l = T[rr * ts + cl];
+        T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+      }
     }
+    __syncthreads();
+    publish(c1, nbest);
+    // the rest of column c's update, while the other workgroups publish
+    update(cl, rs, nr, cl + 2, jb, rw, rc1);
     __syncthreads();
   }
 
@@ -264,50 +304,59 @@ __global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, i
   }
 }
 
-// U12 = L11^-1 A12 (L11 unit lower, jb x jb at A[j][j]); one wave per column
-// of A12, four columns per workgroup; lane t holds rows j + t + 64 u of its
-// column.  L11 is staged in LDS kTrsmCols columns at a time (shared by the
-// workgroup's four waves), so the dependent chain of column steps reads its
-// coefficients from LDS.
-constexpr int kTrsmCols = 32;
+// U12 = L11^-1 A12 (L11 unit lower, jb x jb at A[j][j]); one workgroup per
+// column q of A12, thread r owns row j + r of it and keeps it decoded (window
+// form, plus a NaR flag) across the column steps.  Per column c in ascending
+// order the owner of row c, final once its own last update is in, publishes
+// it through LDS as a pattern and decoded (double-buffered by parity); after
+// one barrier every row r > c gets x[r] - rnd(L11[r][c] x[c]).  Each thread
+// reads its own row of L11, contiguous in memory, kTrsmPrefetch coefficients
+// ahead.
+constexpr int kTrsmPrefetch = 8;
 
 __global__ void __launch_bounds__(256)
 trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb) {
-  __shared__ uint32_t Ls[kMaxNB][kTrsmCols + 1];
-  const int lane = threadIdx.x & 63;
-  const int64_t q = j + jb + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const bool active = q < n;                      // every wave still stages and syncs
-  uint32_t v[4];
+  __shared__ uint32_t xc_p[2];
+  __shared__ dec xc_d[2];
+  const int t = threadIdx.x;
+  const int64_t q = j + jb + blockIdx.x;
+  const bool mine = t < jb;
+  const uint32_t x0 = mine ? A[(j + t) * lda + q] : 0u;
+  bool xnar = x0 == kNaR;
+  win x = win_of(xnar ? 0u : x0);
+  const uint32_t* Lrow = A + (j + (mine ? t : 0)) * lda + j;
+  uint32_t cur[kTrsmPrefetch], nxt[kTrsmPrefetch];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t r = lane + 64 * u;
-    v[u] = active && r < jb ? A[(j + r) * lda + q] : 0u;
-  }
-  for (int c0 = 0; c0 < jb; c0 += kTrsmCols) {
-    const int w = (int)min((int64_t)kTrsmCols, jb - c0);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < jb * w; idx += 256) {
-      const int r = idx / w, cl = idx - r * w;
-      Ls[r][cl] = A[(j + r) * lda + j + c0 + cl];
+  for (int i = 0; i < kTrsmPrefetch; ++i) cur[i] = i < t && mine ? Lrow[i] : 0u;
+  int par = 0;
+  for (int c0 = 0; c0 < jb; c0 += kTrsmPrefetch) {
+#pragma unroll
+    for (int i = 0; i < kTrsmPrefetch; ++i) {
+      const int c = c0 + kTrsmPrefetch + i;       // next chunk, only columns left of row t
+      nxt[i] = c < t && mine ? Lrow[c] : 0u;
     }
-    __syncthreads();
-    if (!active) continue;
-    for (int cl = 0; cl < w; ++cl) {
-      const int c = c0 + cl;
-      const uint32_t bc = __shfl(pick4(v, c >> 6), c & 63);   // final value of row c
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = lane + 64 * u;
-        if (r > c && r < jb) v[u] = p_fms(v[u], Ls[r][cl], bc);
+    for (int i = 0; i < kTrsmPrefetch; ++i) {
+      const int c = c0 + i;
+      if (c < jb) {
+        if (t == c) {
+          const uint32_t pc = xnar ? kNaR : encode_win(x);
+          xc_p[par] = pc;
+          xc_d[par] = decode(pc);
+        }
+        __syncthreads();
+        if (t > c && mine) {
+          const uint32_t l = cur[i], xp = xc_p[par];
+          if (l == kNaR || xp == kNaR) xnar = true;
+          else if (!xnar) x = fms_win(x, decode(l), xc_d[par]);
+        }
+        par ^= 1;
       }
     }
-  }
-  if (!active) return;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t r = lane + 64 * u;
-    if (r < jb) A[(j + r) * lda + q] = v[u];
+    for (int i = 0; i < kTrsmPrefetch; ++i) cur[i] = nxt[i];
   }
+  if (mine) A[(j + t) * lda + q] = xnar ? kNaR : encode_win(x);
 }
 
 // ---- Cholesky --------------------------------------------------------------
@@ -398,17 +447,25 @@ trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t
   const int64_t r = r_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= r_end) return;
   uint32_t* row = A + r * lda + j;
-  uint32_t v = lane < w ? row[lane] : 0u;
+  // lane c's value, kept decoded (window form plus a NaR flag)
+  const uint32_t v0 = lane < w ? row[lane] : 0u;
+  bool vnar = v0 == kNaR;
+  win v = win_of(vnar ? 0u : v0);
   for (int c = 0; c < w; ++c) {
     uint32_t xc = 0u;
     if (lane == c) {
-      xc = p_div(v, Ls[c][c]);
-      v = xc;
+      xc = p_div(vnar ? kNaR : encode_win(v), Ls[c][c]);
+      vnar = xc == kNaR;
+      v = win_of(vnar ? 0u : xc);
     }
     xc = __shfl(xc, c);
-    if (lane > c && lane < w) v = p_fms(v, xc, Ls[lane][c]);
+    if (lane > c && lane < w) {
+      const uint32_t m = Ls[lane][c];
+      if (m == kNaR || xc == kNaR) vnar = true;
+      else if (!vnar) v = fms_win(v, decode(xc), decode(m));
+    }
   }
-  if (lane < w) row[lane] = v;
+  if (lane < w) row[lane] = vnar ? kNaR : encode_win(v);
 }
 
 // ---- triangular solves -----------------------------------------------------
@@ -421,58 +478,57 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
   return kind == 3 ? M[c * lda + r] : M[r * lda + c];
 }
 
-// Diagonal block [s, s+bs) of the solve for one right-hand side q (one
-// workgroup per right-hand side).  Thread r owns row s + r in a register; the
-// coefficients are staged in LDS kCoefCols columns at a time.  Per column c
-// (in solve order) the owner of row c, whose value is final once its own last
-// update is in, divides it by the diagonal (non-unit kinds) and publishes it
-// through LDS; after one barrier every later row r gets
-// x[r] - rnd(T(r,c) x[c]).  The published value is double-buffered by column
-// parity, so one barrier per column suffices.
-constexpr int kTrsvBlock = 256;
-constexpr int kCoefCols = 32;
+// Diagonal block [s, s+bs) (bs <= kTrsvBlock = 64) of the solve for one
+// right-hand side q: one wave per right-hand side, lane r owns row s + r and
+// keeps it decoded (window form plus a NaR flag).  The block's coefficients
+// are staged in LDS once; then, per column c in solve order, the owner lane
+// of row c (final once its own last update is in) divides it by the diagonal
+// (non-unit kinds) and broadcasts it with a wave shuffle, and every later row
+// r gets x[r] - rnd(T(r,c) x[c]).  No barrier inside the chain.
+constexpr int kTrsvBlock = 64;
 
 __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
                  int64_t nrhs, int64_t s, int bs, int kind) {
-  __shared__ uint32_t coef[kTrsvBlock][kCoefCols + 1];
-  __shared__ uint32_t diag[kCoefCols];
-  __shared__ uint32_t xc_sh[2];
+  __shared__ uint32_t coef[kTrsvBlock][kTrsvBlock + 1];
+  __shared__ uint32_t diag[kTrsvBlock];
   const bool forward = kind == 0 || kind == 2;
   const bool unit = kind == 0;
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
-  uint32_t x = t < bs ? B[(s + t) * ldb + q] : 0u;
-  int parity = 0;
-  for (int step0 = 0; step0 < bs; step0 += kCoefCols) {
-    const int steps = min(kCoefCols, bs - step0);
-    __syncthreads();
-    for (int idx = t; idx < bs * steps; idx += kTrsvBlock) {
-      int r, u;
-      if (kind == 3) { u = idx / bs; r = idx - u * bs; }   // row c of M is contiguous in r
-      else { r = idx / steps; u = idx - r * steps; }
-      const int64_t c = forward ? s + step0 + u : s + bs - 1 - step0 - u;
-      coef[r][u] = tri_coef(M, lda, kind, s + r, c);
+  if (!unit && lane < bs) diag[lane] = M[(s + lane) * lda + s + lane];
+  // coef[r][u]: coefficient of the u-th column in solve order in row r
+  for (int idx = lane; idx < bs * bs; idx += kTrsvBlock) {
+    int r, u;
+    if (kind == 3) { u = idx / bs; r = idx - u * bs; }     // row c of M is contiguous in r
+    else { r = idx / bs; u = idx - r * bs; }
+    const int64_t c = forward ? s + u : s + bs - 1 - u;
+    coef[r][u] = tri_coef(M, lda, kind, s + r, c);
+  }
+  const uint32_t x0 = lane < bs ? B[(s + lane) * ldb + q] : 0u;
+  bool xnar = x0 == kNaR;
+  win x = win_of(xnar ? 0u : x0);
+  __syncthreads();
+  for (int u = 0; u < bs; ++u) {
+    const int cl = forward ? u : bs - 1 - u;                // local column
+    uint32_t pc = 0u;
+    if (lane == cl) {
+      pc = xnar ? kNaR : encode_win(x);
+      if (!unit) {
+        pc = p_div(pc, diag[cl]);
+        xnar = pc == kNaR;
+        x = win_of(xnar ? 0u : pc);
+      }
     }
-    if (!unit)
-      for (int u = t; u < steps; u += kTrsvBlock) {
-        const int64_t c = forward ? s + step0 + u : s + bs - 1 - step0 - u;
-        diag[u] = M[c * lda + c];
-      }
-    __syncthreads();
-    for (int u = 0; u < steps; ++u, parity ^= 1) {
-      const int cl = forward ? step0 + u : bs - 1 - step0 - u;   // local column
-      if (t == cl) {
-        if (!unit) x = p_div(x, diag[u]);
-        xc_sh[parity] = x;
-      }
-      __syncthreads();
-      const uint32_t xc = xc_sh[parity];
-      const bool below = forward ? t > cl : t < cl;
-      if (t < bs && below) x = p_fms(x, coef[t][u], xc);
+    pc = __shfl(pc, cl);
+    const bool below = forward ? lane > cl : lane < cl;
+    if (lane < bs && below) {
+      const uint32_t m = coef[lane][u];
+      if (m == kNaR || pc == kNaR) xnar = true;
+      else if (!xnar) x = fms_win(x, decode(m), decode(pc));
     }
   }
-  if (t < bs) B[(s + t) * ldb + q] = x;
+  if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(x);
 }
 
 // rows outside the diagonal block [s, s+bs) get that block's columns, in
@@ -484,12 +540,16 @@ __global__ void trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, 
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (r1 - r0) * nrhs) return;
   const int64_t r = r0 + idx / nrhs, q = idx % nrhs;
-  uint32_t x = B[r * ldb + q];
+  const uint32_t x0 = B[r * ldb + q];
+  bool xnar = x0 == kNaR;                         // the running value, kept decoded
+  win x = win_of(xnar ? 0u : x0);
   for (int64_t step = 0; step < bs; ++step) {
     const int64_t c = forward ? s + step : s + bs - 1 - step;
-    x = p_fms(x, tri_coef(M, lda, kind, r, c), B[c * ldb + q]);
+    const uint32_t m = tri_coef(M, lda, kind, r, c), b = B[c * ldb + q];
+    if (m == kNaR || b == kNaR) xnar = true;
+    else if (!xnar) x = fms_win(x, decode(m), decode(b));
   }
-  B[r * ldb + q] = x;
+  B[r * ldb + q] = xnar ? kNaR : encode_win(x);
 }
 
 // row interchanges of getrs, in order, one thread per right-hand side
@@ -593,8 +653,7 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
                          n, j, jb, ipiv);
     const int64_t rest = n - j - jb;
     if (rest > 0) {
-      hipLaunchKernelGGL(trsm_lu_kernel, dim3((unsigned)((rest + 3) / 4)), dim3(256), 0, s, A, lda, n, j,
-                         jb);
+      hipLaunchKernelGGL(trsm_lu_kernel, dim3((unsigned)rest), dim3(256), 0, s, A, lda, n, j, jb);
       rc = launch_gemm_ex(s, 0, 0, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
                           A + j * lda + j + jb, lda, kOne, A + (j + jb) * lda + j + jb, lda, false,
                           nullptr);

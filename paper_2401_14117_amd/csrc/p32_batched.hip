@@ -51,7 +51,14 @@ namespace p32 {
 namespace {
 
 constexpr int kBT = NT;          // threads per workgroup (the tile routine needs NT)
-constexpr int kSub = 32;         // sub-panel / sub-block width
+#ifndef P32_BATCH_KSUB
+#define P32_BATCH_KSUB 32
+#endif
+constexpr int kSub = P32_BATCH_KSUB;   // sub-panel / sub-block width
+#ifndef P32_BATCH_UNROLL
+#define P32_BATCH_UNROLL 4
+#endif
+constexpr int kUnroll = P32_BATCH_UNROLL;   // k-steps unrolled in the tile routine
 constexpr uint32_t kMinus1 = 0xC0000000u;
 
 struct Shared {
@@ -85,7 +92,7 @@ __device__ __forceinline__ void tiles(int64_t m, int64_t n, int64_t k, const uin
   if (m <= 0 || n <= 0 || k <= 0) return;
   const int64_t nr = (m + BM - 1) / BM, nc = (n + BN - 1) / BN;
   for (int64_t t = 0; t < nr * nc; ++t)
-    gemm_tile<TA, TB, LOWER, CHAIN, REVK>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, (t / nc) * BM,
+    gemm_tile<TA, TB, LOWER, CHAIN, REVK, kUnroll>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, (t / nc) * BM,
                                           (t % nc) * BN, sh.tile);
   __syncthreads();
 }

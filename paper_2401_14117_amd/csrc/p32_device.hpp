@@ -252,13 +252,15 @@ __device__ inline uint32_t sqrt_general(dec a, bool a_nar) {
 // fast path: multiply and add in window form
 // ---------------------------------------------------------------------------
 
+// LLVM's AMDGPU intrinsics for v_ffbh_i32 and v_mul_i32_i24, called directly
+// (no clang builtin exposes them); unlike inline asm they leave the
+// instruction scheduler and the hazard recognizer full knowledge.
+extern "C" __device__ __attribute__((const)) int p32_llvm_sffbh(int) __asm("llvm.amdgcn.sffbh.i32");
+extern "C" __device__ __attribute__((const)) int p32_llvm_mul_i24(int, int) __asm("llvm.amdgcn.mul.i24");
+
 // v_ffbh_i32: position (counted from bit 31) of the first bit that differs
 // from the sign bit; -1 for 0 and -1.
-__device__ __forceinline__ int ffbh_i32(int32_t x) {
-  int r;
-  asm("v_ffbh_i32 %0, %1" : "=v"(r) : "v"(x));
-  return r;
-}
+__device__ __forceinline__ int ffbh_i32(int32_t x) { return p32_llvm_sffbh(x); }
 
 __device__ __forceinline__ uint32_t bfm(int width) {   // (1 << width) - 1
   uint32_t r;

@@ -14,10 +14,17 @@
 // n are staged as 1.0 (their results are discarded); k beyond the end is
 // staged as exact zero, which leaves the accumulators unchanged.
 //
-// Inside the kernel every window exponent carries the bias EB, so that
-// exponent differences can use unsigned saturating subtraction, and
-// EB = 128 (mod 256) makes the low byte of a biased exponent the index of its
-// entry in the per-workgroup table of rounding parameters (scales -128..127).
+// Inside the kernel every window exponent carries the bias EB = 128 (mod 256),
+// so that the low byte of an aligned exponent minus the sum's leading-bit
+// count indexes the per-workgroup table of rounding parameters (scales
+// -124..131), whose entries also hold the biased exponent of the result.  In
+// a k-tile whose operands and accumulators are proven to stay in the fast
+// range, one k-step per multiply-add is: a 64-bit product, its leading-bit
+// count, a table lookup, normalisation with a round-to-odd sticky bit and
+// rounding at the table's position; then one shift aligns the smaller of
+// product and accumulator, a 32-bit add on the high word forms the exact sum,
+// and the same count / lookup / round sequence rounds it.  The k-steps of
+// such a tile are unrolled.
 #include <hip/hip_runtime.h>
 
 #include "p32_device.hpp"

@@ -22,9 +22,11 @@ namespace p32 {
 #define P32_GEMM_TN 2             // columns of C per thread
 #endif
 
-#ifndef P32_GEMM_LUT4
-#define P32_GEMM_LUT4 1           // 16-byte rounding-table entries (no unpacking shift)
+#ifndef P32_GEMM_UNROLL
+#define P32_GEMM_UNROLL 16        // k-steps of a proven k-tile unrolled per loop iteration
 #endif
+#define P32_STR_(x) #x
+#define P32_UNROLL_(n) _Pragma(P32_STR_(unroll n))
 
 #ifndef P32_GEMM_BK
 #define P32_GEMM_BK 16            // k-tile depth staged per barrier pair
@@ -35,6 +37,11 @@ constexpr int BM = 16 * TM, BN = 16 * TN;   // 16 x 16 threads per workgroup
 constexpr unsigned GROUP_M = 8;             // tile rows per group of the tile order
 constexpr int EB = 8192 + 128;           // exponent bias inside the kernel
 constexpr int kEZeroB = kEZero + EB;     // biased exponent of zero (> 0)
+// Entry i of the rounding table describes scale i - kLutShift.  A sum whose
+// aligned exponent is E and whose leading-bit count is cnt has scale
+// E + 4 - cnt - EB, i.e. entry (E - cnt) mod 256 since EB = 128 (mod 256);
+// a product of staged operands has entry sa + sb + 128 - cnt (see below).
+constexpr int kLutShift = 124;
 
 // ---- rare path: exact multiply-add for one element (unbiased interface) ----
 static __device__ __noinline__ win madd_slow(win acc, int32_t a8, int32_t sca, int32_t b4, int32_t scb) {
@@ -73,16 +80,25 @@ __device__ __forceinline__ win bias(win u) {
   return w;
 }
 
+// ---- staged operands --------------------------------------------------------
+// op(A) element: (s << 3, 16 * (sc + 128)); op(B) element: (s << 2, 16 * sc).
+// The scales are kept premultiplied by 16, the size of a rounding-table
+// entry, so that a product's table offset is one add and one multiply-add.
+__device__ __forceinline__ int2 stage_a(dec d, bool neg) {
+  return make_int2((neg ? -d.s : d.s) * 8, 16 * (d.sc + 128));
+}
+__device__ __forceinline__ int2 stage_b(dec d) { return make_int2(d.s * 4, 16 * d.sc); }
+__device__ __forceinline__ int scale_a(int2 a) { return (a.y >> 4) - 128; }
+__device__ __forceinline__ int scale_b(int2 b) { return b.y >> 4; }
+
 // ---- checked fast path (any operands; flags what it does not cover) --------
-// staged operand a = (s_a << 3, sc_a + EB + 4), b = (s_b << 2, sc_b)
 __device__ __forceinline__ bool mul_checked(int2 a, int2 b, win& out) {
   const int64_t P = (int64_t)a.x * (int64_t)b.x;       // |P| in [2^59, 2^61)
   const int cnt = ffbh_i32((int32_t)(P >> 32));
   const int c3 = cnt - 3;
-  const int eb = a.y + b.y - cnt;                      // biased scale
-  const int sc = eb - EB;
+  const int sc = scale_a(a) + scale_b(b) + 4 - cnt;
   out.h = round_h2(fold_sticky((uint64_t)P << (c3 & 63)), sc).h;
-  out.e = eb;
+  out.e = sc + EB;
   return ((unsigned)c3 < 3u) & scale_ok(sc);
 }
 
@@ -100,43 +116,63 @@ __device__ __forceinline__ bool add_checked(win a, win b, win& out) {
 }
 
 // ---- unchecked fast path (operands proven in range for the whole k-tile) ---
-// The rounding parameters come from the LDS table; exponent differences use
-// saturating subtraction and the one test left covers cancellation (c3 < 0)
-// and alignments of 64 bits or more, which go to the exact path.
-#if P32_GEMM_LUT4
-typedef uint4 lut_t;
-__device__ __forceinline__ lut_t make_lut_entry(int sc) { return round_params4(sc); }
-__device__ __forceinline__ int32_t round_entry(int32_t h2, lut_t p) { return round_lut4(h2, p); }
-#else
-typedef uint2 lut_t;
-__device__ __forceinline__ lut_t make_lut_entry(int sc) { return round_params(sc); }
-__device__ __forceinline__ int32_t round_entry(int32_t h2, lut_t p) { return round_lut(h2, p); }
-#endif
+// Rounding parameters and the result exponent come from the LDS table.  The
+// one test left covers cancellation of the sum's high word (c3 < 0) and
+// alignments of 64 bits or more, which go to the exact path.
+typedef uint4 lut_t;    // x = r, y = 2^(r-1) - 1, z = ~(2^r - 1), w = biased exponent
+__device__ __forceinline__ lut_t make_lut_entry(int i) {
+  const int sc = i - kLutShift;
+  const uint2 p = round_params(sc);
+  return make_uint4(p.x & 31u, p.x >> 5, p.y, (uint32_t)(sc + EB));
+}
+__device__ __forceinline__ const lut_t& lut_at(const lut_t* lut, uint32_t byte_off) {
+  return *(const lut_t*)((const char*)lut + byte_off);
+}
+
+// x * y + z on the low 24 bits of x and y (one v_mad_i32_i24)
+__device__ __forceinline__ int32_t mad_i24(int32_t x, int32_t y, int32_t z) {
+  return p32_llvm_mul_i24(x, y) + z;
+}
+
+// |x - y| for unsigned x, y (v_sad_u32 with a zero accumulator)
+__device__ __forceinline__ uint32_t absdiff(uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
 
 __device__ __forceinline__ win mul_unchecked(int2 a, int2 b, const lut_t* __restrict__ lut) {
   const int64_t P = (int64_t)a.x * (int64_t)b.x;
   const int cnt = ffbh_i32((int32_t)(P >> 32));
-  const int eb = a.y + b.y - cnt;
-  const lut_t rp = lut[eb & 255];
+  // 16 * (sa + sb + 128 - cnt): entry of scale sa + sb + 4 - cnt
+  const lut_t rp = lut_at(lut, (uint32_t)mad_i24(cnt, -16, a.y + b.y));
+  const int eb = (int)rp.w;
   win w;
-  w.h = round_entry(fold_sticky((uint64_t)P << ((cnt - 3) & 63)), rp);
+  w.h = round_lut4(fold_sticky((uint64_t)P << ((cnt - 3) & 63)), rp);
   w.e = eb;
   return w;
 }
 
+// The operand with the larger exponent is added to the high word of the other
+// one shifted right by the exponent difference: the same 64-bit sum as
+// aligning both to the larger exponent, with one shift instead of two.
 __device__ __forceinline__ win add_unchecked(win a, win b, const lut_t* __restrict__ lut,
                                              uint32_t& badbits) {
-  const uint32_t db = __builtin_elementwise_sub_sat((uint32_t)a.e, (uint32_t)b.e);
-  const uint32_t da = __builtin_elementwise_sub_sat((uint32_t)b.e, (uint32_t)a.e);
-  const int E4 = b.e + (int)db + 4;                     // max(a.e, b.e) + 4
-  const int64_t S = (((int64_t)a.h << 32) >> da) + (((int64_t)b.h << 32) >> db);
-  const int cnt = ffbh_i32((int32_t)(S >> 32));
+  const uint32_t d = absdiff((uint32_t)a.e, (uint32_t)b.e);
+  const bool bbig = b.e > a.e;
+  const int32_t big = bbig ? b.h : a.h;
+  const int32_t small = bbig ? a.h : b.h;
+  const int E = bbig ? b.e : a.e;
+  const int64_t Y = ((int64_t)small << 32) >> (d & 63);
+  const int32_t Shi = (int32_t)(Y >> 32) + big;        // the low word of big << 32 is 0
+  const uint64_t S = ((uint64_t)(uint32_t)Shi << 32) | (uint32_t)Y;
+  const int cnt = ffbh_i32(Shi);
   const int c3 = cnt - 3;
-  badbits |= da | db | (uint32_t)c3;                    // > 63 means: exact path
-  const int eb = E4 - cnt;
-  const lut_t rp = lut[eb & 255];
+  badbits |= d | (uint32_t)c3;                          // > 63 means: exact path
+  const lut_t rp = lut[(uint32_t)(E - cnt) & 255u];   // entry of scale E + 4 - cnt - EB
+  const int eb = (int)rp.w;
   win w;
-  w.h = round_entry(fold_sticky((uint64_t)S << (c3 & 63)), rp);
+  w.h = round_lut4(fold_sticky(S << (c3 & 63)), rp);
   w.e = eb;
   return w;
 }
@@ -174,7 +210,7 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        nacc[i][j] = bias(madd_slow(unbias(acc[i][j]), a[i].x, a[i].y - EB - 4, b[j].x, b[j].y));
+        nacc[i][j] = bias(madd_slow(unbias(acc[i][j]), a[i].x, scale_a(a[i]), b[j].x, scale_b(b[j])));
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -195,13 +231,15 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
 // substitutions of the solves, whose updates come in descending column order).
 // LDS of one tile computation; the caller declares it once per kernel
 struct TileLds {
-  int2 As[BK][BM];   // (s << 3, scale + EB + 4) of op(A)(i0 + i, p0 + p)
-  int2 Bs[BK][BN];   // (s << 2, scale) of op(B)(p0 + p, j0 + j)
-  lut_t lut[256];    // rounding parameters of scales -128..127
+  int2 As[BK][BM];   // stage_a of op(A)(i0 + i, p0 + p)
+  int2 Bs[BK][BN];   // stage_b of op(B)(p0 + p, j0 + j)
+  lut_t lut[256];    // rounding parameters of scales -124..131
   int rowNaR[BM], colNaR[BN];
 };
 
-template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK = false>
+// UNROLL: k-steps of a proven k-tile unrolled per loop iteration (code size
+// against loop overhead; the Rgemm kernel unrolls the whole k-tile).
+template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK = false, int UNROLL = P32_GEMM_UNROLL>
 __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A,
                                           int64_t lda, const uint32_t* __restrict__ B, int64_t ldb,
                                           uint32_t* __restrict__ C, int64_t ldc, uint32_t alpha,
@@ -218,7 +256,7 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
   __syncthreads();                                // LDS of a previous tile no longer in use
   if (tid < BM) rowNaR[tid] = 0;
   if (tid < BN) colNaR[tid] = 0;
-  lut[tid] = make_lut_entry(tid - 128);   // NT == 256 entries
+  lut[tid] = make_lut_entry(tid);   // NT == 256 entries
 
   win acc[TM][TN];
   uint32_t cnar = 0;            // CHAIN: bit i*TN+j set when C_ij starts as NaR
@@ -255,7 +293,7 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
       if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
       const dec d = decode(v);
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
-      As[pp][ii] = make_int2((CHAIN ? -d.s : d.s) * 8, d.sc + EB + 4);
+      As[pp][ii] = stage_a(d, CHAIN);
     }
 #pragma unroll
     for (int l = 0; l < (BN * BK) / NT; ++l) {
@@ -271,7 +309,7 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
       if (v == kNaR) { colNaR[jj] = 1; v = kOne; }
       const dec d = decode(v);
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
-      Bs[pp][jj] = make_int2(d.s * 4, d.sc);
+      Bs[pp][jj] = stage_b(d);
     }
     // Block-uniform choice of the inner loop for this k-tile.  The unchecked
     // loop is exact when every staged operand is nonzero with scale in
@@ -290,17 +328,21 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
         my_ok &= (acc[i][j].h == 0) | ((unsigned)(acc[i][j].e - EB + 106) <= 206u);
     const bool safe = __syncthreads_and(my_ok);
 
-    int p = 0;
     if (p0 == 0) {        // first step: accumulators not yet tested, use the checked path
       k_step<true>(acc, As[0], Bs[0], lut, tx, ty);
-      p = 1;
-    }
-    if (safe) {
+      if (safe) {
 #pragma unroll 1
-      for (; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
+        for (int p = 1; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
+      } else {
+#pragma unroll 1
+        for (int p = 1; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
+      }
+    } else if (safe) {
+      P32_UNROLL_(UNROLL)
+      for (int p = 0; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
     } else {
 #pragma unroll 1
-      for (; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
+      for (int p = 0; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
     }
   }
   __syncthreads();

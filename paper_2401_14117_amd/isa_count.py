@@ -1,11 +1,14 @@
 """Count the VALU instructions per multiply-add in the Rgemm kernel's ISA.
 
-The fast path of one k step of the NN kernel is the straight-line block that
-begins at the inner k-loop header and ends at the branch into the rare exact
-path; it performs TM*TN multiply-adds.  Its VALU instruction count divided by
-TM*TN is the kernel's cost per multiply-add in VALU issue slots (each a
-64-lane wave instruction).  build.py records it next to the library so the
-benchmark can express the kernel's throughput as a fraction of the VALU peak.
+The fast path of one k step of the NN kernel is a straight-line block that
+ends at the branch into the rare exact path; it performs TM*TN multiply-adds
+and is recognised by its TM*TN 64-bit products (v_mad_i64_i32) and TM*TN
+exponent differences (v_sad_u32, used only by the unchecked sum).  The
+k-steps of a proven k-tile are unrolled, so there is one such block per step;
+the median VALU instruction count of these blocks divided by TM*TN is the
+kernel's cost per multiply-add in VALU issue slots (each a 64-lane wave
+instruction).  build.py records it next to the library so the benchmark can
+express the kernel's throughput as a fraction of the VALU peak.
 """
 from __future__ import annotations
 
@@ -32,14 +35,25 @@ def count(asm_text: str) -> dict:
     lines = asm_text.splitlines()
     start = next(i for i, l in enumerate(lines) if l.startswith(KERNEL + ":"))
     end = next(i for i in range(start, len(lines)) if "s_endpgm" in lines[i])
-    body = lines[start:end]
-    head = next(i for i, l in enumerate(body) if "Inner Loop Header: Depth=2" in l)
-    stop = next(i for i in range(head + 1, len(body)) if "s_cbranch" in body[i])
-    insts = [l.split()[0] for l in body[head + 1:stop] if re.match(r"\s+[vsd][a-z_0-9]+", l)]
-    valu = [x for x in insts if x.startswith("v_")]
+    blocks, cur = [], []
+    for line in lines[start:end]:
+        # a block ends at a branch and restarts where divergent paths rejoin
+        if re.match(r"\s+s_cbranch", line) or re.match(r"\s+s_or_b64\s+exec, exec", line):
+            blocks.append(cur)
+            cur = []
+        elif re.match(r"\s+[vsd][a-z_0-9]+", line):
+            cur.append(line.split()[0])
+    steps = [b for b in blocks
+             if b.count("v_mad_i64_i32") == MADDS_PER_STEP and b.count("v_sad_u32") == MADDS_PER_STEP]
+    if not steps:
+        raise RuntimeError("fast k-step block not found in the Rgemm kernel's ISA")
+    sizes = sorted(sum(x.startswith("v_") for x in b) for b in steps)
+    step = next(b for b in steps if sum(x.startswith("v_") for x in b) == sizes[len(sizes) // 2])
+    valu = [x for x in step if x.startswith("v_")]
     return {"valu_per_step": len(valu), "valu_per_madd": len(valu) / MADDS_PER_STEP,
-            "lds_per_step": sum(x.startswith("ds_") for x in insts),
-            "salu_per_step": sum(x.startswith("s_") for x in insts)}
+            "lds_per_step": sum(x.startswith("ds_") for x in step),
+            "salu_per_step": sum(x.startswith("s_") for x in step),
+            "steps_found": len(steps)}
 
 
 def write_report(hipcc: str, flags: list[str], out_path: str) -> dict:

@@ -341,6 +341,15 @@ def run_batch_bench(name: str, args, dev) -> dict:
     return _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args)
 
 
+def _tuning_info(kind: str) -> dict:
+    """The sub-panel table the batched kernels ran with, and where it came from."""
+    from paper_2401_14117_amd import posit32
+    t = posit32.active_tuning(kind)
+    src = posit32.tuning_file() if t is not None else "built-in"
+    t = t if t is not None else posit32.default_tuning(kind)
+    return {"source": os.path.relpath(src, ROOT) if src != "built-in" else src, **t.to_dict()}
+
+
 def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args) -> dict:
     return {
         "metric": f"Posit32 batched {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s",
@@ -351,7 +360,7 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
         "config": {"workload": name, "count": count, "n": "round(exp(U(ln 16, ln 512)))",
                    "nrhs": "1..16", "nb": args.nb, "factor_gpops": round(pops / (kms * 1e-3) / 1e9, 1),
                    "info_nonzero": int(np.count_nonzero(info)), "setup_s": round(setup_s, 1),
-                   "one_at_a_time": single},
+                   "sub_panel_tuning": _tuning_info(kind), "one_at_a_time": single},
         "roofline": None,
         "cpu_baseline": cpu,
     }

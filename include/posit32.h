@@ -219,6 +219,65 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
                           posit32_t* const* B, const int64_t* ldb, int32_t* info);
 
 /*
+ * Tuned variable-size batches.  posit32_vbatched runs any of the six batched
+ * calls above from one descriptor, with an explicit tuning table; apart from
+ * the table nothing changes (same validation, same per-system info, same
+ * bits).  The six calls above use the built-in table.
+ *
+ * The batched kernels factor each panel in sub-panels of `sub` columns (the
+ * unblocked pivot search / division / rank-1 updates inside, fused-update
+ * chains through the Rgemm tile routine outside; the solves work in blocks of
+ * `sub` rows).  The width only regroups the work -- every element receives
+ * its updates in the unblocked order -- so every table gives the same result
+ * bits; it changes only the speed.  A system of order n uses sub[b] of the
+ * first bucket b with n <= max_n[b] (the last bucket takes every larger n).
+ * paper_2401_14117_amd/autotune.py measures the fastest width per bucket on
+ * the device and stores the tables it finds.
+ *
+ *   posit32_vbatch_tuning: buckets in [1, P32_TUNE_BUCKETS]; max_n strictly
+ *     ascending over the used buckets; sub in [1, 64].
+ *   posit32_vbatch: kind 0 (LU, as P32_REQ_LU below) or 1 (Cholesky);
+ *     factor / solve 0 or 1, at least one set; the other fields as the
+ *     arguments of the calls above (ipiv only for LU; nrhs, B, ldb only with
+ *     solve; nb only with factor).
+ * posit32_vbatched(stream, batch, tuning): tuning NULL = the built-in table
+ *   of batch->kind.  Host-side validation only; allocates nothing, one launch
+ *   (graph-capturable: the table is copied into the launch arguments).
+ *   Errors: -2 batch NULL or any descriptor field invalid (the checks of the
+ *   calls above), -3 tuning invalid.
+ * posit32_vbatched_default_tuning(kind, out): copies the built-in table of
+ *   kind (0 LU, 1 Cholesky) to *out (host memory).  Errors: -1 bad kind,
+ *   -2 out NULL.
+ */
+#define P32_TUNE_BUCKETS 8
+
+typedef struct {
+  int32_t buckets;
+  int32_t max_n[P32_TUNE_BUCKETS];
+  int32_t sub[P32_TUNE_BUCKETS];
+} posit32_vbatch_tuning;
+
+typedef struct {
+  int32_t kind;              /* 0 LU, 1 Cholesky */
+  int32_t factor;            /* 1: factor A */
+  int32_t solve;             /* 1: solve with B (after the factorisation, or with given factors) */
+  int32_t count;
+  int32_t max_n;
+  int64_t nb;
+  const int32_t* n;
+  const int32_t* nrhs;
+  posit32_t* const* A;
+  const int64_t* lda;
+  int32_t* const* ipiv;
+  posit32_t* const* B;
+  const int64_t* ldb;
+  int32_t* info;
+} posit32_vbatch;
+
+int posit32_vbatched(void* stream, const posit32_vbatch* batch, const posit32_vbatch_tuning* tuning);
+int posit32_vbatched_default_tuning(int kind, posit32_vbatch_tuning* out);
+
+/*
  * Request queue (serving): many independent systems of different sizes,
  * submitted one by one from host memory and solved with continuous batching
  * on the device current at creation.  The queue owns one worker thread, two
@@ -236,7 +295,9 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
  *  - Each system is factored and solved exactly as posit32_gesv_vbatched /
  *    posit32_posv_vbatched (or the single-matrix calls) with block size
  *    cfg->nb would do it: the solution is bit-identical however requests are
- *    batched.
+ *    batched.  cfg->tuning (NULL = built-in) points to two sub-panel tables,
+ *    [0] for LU and [1] for Cholesky, copied at creation (see
+ *    posit32_vbatched).
  *  - keep = 1 keeps a successful factorisation resident; the handle comes
  *    back in posit32_result.factor.  A later request with factor = handle
  *    (same kind and n, A ignored) is solved with it without refactoring.
@@ -251,7 +312,8 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
  * with info > 0 is not solved and not kept (X is then the unsolved B).  Times
  * are seconds on the host's monotonic clock since the queue was created.
  * All calls are thread-safe.  Errors: -1 bad queue or cfg (device_bytes below
- * 1 MiB, max_batch < 1, nb outside 1..256, batch_max_n < 0), -2 bad request,
+ * 1 MiB, max_batch < 1, nb outside 1..256, batch_max_n < 0, invalid tuning
+ * table), -2 bad request,
  * ticket or factor handle, P32_E_NOMEM from submit for a system larger than
  * the pool.  posit32_queue_destroy finishes every submitted request first.
  */
@@ -265,6 +327,7 @@ typedef struct {
   int32_t max_batch;         /* most systems per batch */
   int32_t nb;                /* block size of the factorisations */
   int32_t batch_max_n;       /* largest n sent through the batched kernels */
+  const posit32_vbatch_tuning* tuning;   /* NULL, or [LU, Cholesky] tables */
 } posit32_queue_cfg;
 
 typedef struct {

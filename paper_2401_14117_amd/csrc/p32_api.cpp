@@ -8,7 +8,7 @@
 
 extern "C" {
 
-int posit32_version(void) { return 100; }
+int posit32_version(void) { return 110; }
 
 const char* posit32_strerror(int code) {
   if (code == 0) return "ok";
@@ -183,4 +183,66 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
                               nrhs, B, ldb, info);
 }
 
+static bool tuning_ok(const posit32_vbatch_tuning& t) {
+  if (t.buckets < 1 || t.buckets > P32_TUNE_BUCKETS) return false;
+  for (int b = 0; b < t.buckets; ++b) {
+    if (t.sub[b] < 1 || t.sub[b] > 64) return false;
+    if (b > 0 && t.max_n[b] <= t.max_n[b - 1]) return false;
+  }
+  return true;
+}
+
+static p32::Tuning to_tuning(const posit32_vbatch_tuning& t) {
+  p32::Tuning r{};
+  static_assert(p32::kTuneBuckets == P32_TUNE_BUCKETS, "bucket count of the C ABI and the kernels");
+  r.buckets = t.buckets;
+  for (int b = 0; b < P32_TUNE_BUCKETS; ++b) {
+    r.max_n[b] = t.max_n[b];
+    r.sub[b] = t.sub[b];
+  }
+  return r;
+}
+
+int posit32_vbatched(void* stream, const posit32_vbatch* bt, const posit32_vbatch_tuning* tuning) {
+  if (bt == nullptr) return -2;
+  if (bt->kind != 0 && bt->kind != 1) return -2;
+  if ((bt->factor != 0 && bt->factor != 1) || (bt->solve != 0 && bt->solve != 1)) return -2;
+  if (!bt->factor && !bt->solve) return -2;
+  if (vb_common(bt->count, bt->max_n, bt->n, bt->A, bt->lda, bt->info)) return -2;
+  if (bt->factor && (bt->nb < 1 || bt->nb > 256)) return -2;
+  if (bt->count > 0 && bt->kind == 0 && bt->ipiv == nullptr) return -2;
+  if (bt->count > 0 && bt->solve && (bt->nrhs == nullptr || bt->B == nullptr || bt->ldb == nullptr))
+    return -2;
+  p32::Tuning t{};
+  if (tuning != nullptr) {
+    if (!tuning_ok(*tuning)) return -3;
+    t = to_tuning(*tuning);
+  } else {
+    t = p32::default_tuning(bt->kind);
+  }
+  return p32::launch_vbatched((hipStream_t)stream, bt->kind, bt->factor != 0, bt->solve != 0, bt->count,
+                              bt->max_n, bt->factor ? bt->nb : 1, bt->n, bt->A, bt->lda,
+                              bt->kind == 0 ? bt->ipiv : nullptr, bt->solve ? bt->nrhs : nullptr,
+                              bt->solve ? bt->B : nullptr, bt->solve ? bt->ldb : nullptr, bt->info, &t);
+}
+
+int posit32_vbatched_default_tuning(int kind, posit32_vbatch_tuning* out) {
+  if (kind != 0 && kind != 1) return -1;
+  if (out == nullptr) return -2;
+  const p32::Tuning t = p32::default_tuning(kind);
+  *out = posit32_vbatch_tuning{};
+  out->buckets = t.buckets;
+  for (int b = 0; b < P32_TUNE_BUCKETS; ++b) {
+    out->max_n[b] = t.max_n[b];
+    out->sub[b] = t.sub[b];
+  }
+  return 0;
+}
+
 }  // extern "C"
+
+int p32::tuning_from_abi(const posit32_vbatch_tuning& t, p32::Tuning* out) {
+  if (!tuning_ok(t)) return -1;
+  *out = to_tuning(t);
+  return 0;
+}

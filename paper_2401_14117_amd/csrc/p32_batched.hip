@@ -12,7 +12,7 @@
 // Every matrix is processed in the schedule of the single-matrix routines
 // with the same block size nb, so the results are bit-identical to them:
 //
-//  LU, per panel [j, j+jb): sub-panels of kSub columns [c0, c0+w):
+//  LU, per panel [j, j+jb): sub-panels of `sub` columns [c0, c0+w):
 //    (i)   unblocked LU of the sub-panel on rows [c0, n) (pivot search,
 //          swap inside the sub-panel, scaling, rank-1 updates);
 //    (ii)  the sub-panel's interchanges applied to all other columns;
@@ -38,9 +38,16 @@
 //    Rgemm(-1, 1, L21, L21^T).
 //
 //  Solves: the row interchanges (LU), then forward and backward substitution
-//  in blocks of kSub rows: the diagonal block column by column, then one
+//  in blocks of `sub` rows: the diagonal block column by column, then one
 //  fused-update chain over the block's columns for all rows beyond it (in
 //  descending column order for the backward pass).
+//
+// The sub-panel width `sub` only regroups the work: every element still gets
+// its updates in the unblocked order, so any width gives the same bits.  It
+// is chosen per system from a table of size buckets (the autotuner measures
+// the fastest width of each bucket on the device): narrow sub-panels put more
+// of a large matrix's updates on the tile routine, and a width of at least n
+// factors a small matrix unblocked, with no tile overhead at all.
 #include <hip/hip_runtime.h>
 
 #include "p32_device.hpp"
@@ -51,10 +58,7 @@ namespace p32 {
 namespace {
 
 constexpr int kBT = NT;          // threads per workgroup (the tile routine needs NT)
-#ifndef P32_BATCH_KSUB
-#define P32_BATCH_KSUB 32
-#endif
-constexpr int kSub = P32_BATCH_KSUB;   // sub-panel / sub-block width
+constexpr int kMaxSub = 64;      // widest sub-panel / sub-block
 #ifndef P32_BATCH_UNROLL
 #define P32_BATCH_UNROLL 4
 #endif
@@ -64,10 +68,10 @@ constexpr uint32_t kMinus1 = 0xC0000000u;
 struct Shared {
   TileLds tile;
   unsigned long long red[kBT / 64];
-  uint32_t urow[kSub];
-  dec udec[kSub];
-  uint32_t diag[kSub];
-  int32_t piv[kSub];
+  uint32_t urow[kMaxSub];
+  dec udec[kMaxSub];
+  uint32_t diag[kMaxSub];
+  int32_t piv[kMaxSub];
   int flag;
 };
 
@@ -187,14 +191,14 @@ __device__ __forceinline__ void lu_trsm_rows(uint32_t* A, int64_t lda, int64_t c
   }
 }
 
-__device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int32_t* ipiv,
-                                          int32_t& info, Shared& sh) {
+__device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int sub,
+                                          int32_t* ipiv, int32_t& info, Shared& sh) {
   info = 0;
   for (int64_t j = 0; j < n; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;
     const int64_t je = j + jb;
-    for (int64_t c0 = j; c0 < je; c0 += kSub) {
-      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+    for (int64_t c0 = j; c0 < je; c0 += sub) {
+      const int w = (int)(sub < je - c0 ? sub : je - c0);
       lu_subpanel(A, lda, n, c0, w, ipiv, info, sh);
       lu_laswp(A, lda, n, c0, w, sh);
       const int64_t r1 = c0 + w;                   // first row / column after the sub-panel
@@ -206,8 +210,8 @@ __device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, i
     }
     // U12 = L11^-1 A12, only once every interchange of the panel is in place
     // (a later pivot may bring up a row from below the panel)
-    for (int64_t c0 = j; c0 < je && je < n; c0 += kSub) {
-      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+    for (int64_t c0 = j; c0 < je && je < n; c0 += sub) {
+      const int w = (int)(sub < je - c0 ? sub : je - c0);
       const int64_t r1 = c0 + w;
       lu_trsm_rows(A, lda, c0, w, je, n);
       tiles<false, false, false, true, false>(je - r1, n - je, w, A + r1 * lda + c0, lda,
@@ -221,8 +225,9 @@ __device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, i
 }
 
 // forward (unit lower) and backward (upper) substitution with the LU factors
-__device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_t n, const int32_t* ipiv,
-                                         uint32_t* B, int64_t ldb, int64_t nrhs, Shared& sh) {
+__device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_t n, int sub,
+                                         const int32_t* ipiv, uint32_t* B, int64_t ldb, int64_t nrhs,
+                                         Shared& sh) {
   const int t = threadIdx.x;
   for (int64_t q = t; q < nrhs; q += kBT)
     for (int64_t c = 0; c < n; ++c) {
@@ -234,8 +239,8 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
       }
     }
   __syncthreads();
-  for (int64_t c0 = 0; c0 < n; c0 += kSub) {
-    const int w = (int)(kSub < n - c0 ? kSub : n - c0);
+  for (int64_t c0 = 0; c0 < n; c0 += sub) {
+    const int w = (int)(sub < n - c0 ? sub : n - c0);
     for (int cl = 0; cl + 1 < w; ++cl) {
       const int64_t c = c0 + cl;
       const int64_t cnt = (w - cl - 1) * nrhs;
@@ -250,8 +255,8 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
     tiles<false, false, false, true, false>(n - r1, nrhs, w, LU + r1 * lda + c0, lda, B + c0 * ldb, ldb,
                                             B + r1 * ldb, ldb, 0u, 0u, sh);
   }
-  for (int64_t c1 = n; c1 > 0; c1 -= kSub) {
-    const int64_t c0 = c1 - kSub > 0 ? c1 - kSub : 0;
+  for (int64_t c1 = n; c1 > 0; c1 -= sub) {
+    const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
     for (int64_t c = c1 - 1; c >= c0; --c) {
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], LU[c * lda + c]);
       __syncthreads();
@@ -326,14 +331,14 @@ __device__ __forceinline__ void chol_trsm_rows(uint32_t* A, int64_t lda, int64_t
   }
 }
 
-__device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int32_t& info,
-                                            Shared& sh) {
+__device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n, int64_t nb, int sub,
+                                            int32_t& info, Shared& sh) {
   info = 0;
   for (int64_t j = 0; j < n; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;
     const int64_t je = j + jb;
-    for (int64_t c0 = j; c0 < je; c0 += kSub) {
-      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+    for (int64_t c0 = j; c0 < je; c0 += sub) {
+      const int w = (int)(sub < je - c0 ? sub : je - c0);
       const int64_t r1 = c0 + w;
       const int64_t fail = chol_subblock(A, lda, c0, w, sh);
       const int steps = fail < 0 ? w : (int)(fail - c0);
@@ -347,8 +352,8 @@ __device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n,
     }
     const int64_t rest = n - je;
     if (rest <= 0) continue;
-    for (int64_t c0 = j; c0 < je; c0 += kSub) {
-      const int w = (int)(kSub < je - c0 ? kSub : je - c0);
+    for (int64_t c0 = j; c0 < je; c0 += sub) {
+      const int w = (int)(sub < je - c0 ? sub : je - c0);
       const int64_t c1 = c0 + w;
       chol_trsm_rows(A, lda, je, n, c0, w, w, sh);
       tiles<false, true, false, true, false>(rest, je - c1, w, A + je * lda + c0, lda, A + c1 * lda + c0,
@@ -359,11 +364,11 @@ __device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n,
   }
 }
 
-__device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64_t n, uint32_t* B,
+__device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64_t n, int sub, uint32_t* B,
                                            int64_t ldb, int64_t nrhs, Shared& sh) {
   const int t = threadIdx.x;
-  for (int64_t c0 = 0; c0 < n; c0 += kSub) {
-    const int w = (int)(kSub < n - c0 ? kSub : n - c0);
+  for (int64_t c0 = 0; c0 < n; c0 += sub) {
+    const int w = (int)(sub < n - c0 ? sub : n - c0);
     for (int cl = 0; cl < w; ++cl) {
       const int64_t c = c0 + cl;
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
@@ -380,8 +385,8 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
     tiles<false, false, false, true, false>(n - r1, nrhs, w, L + r1 * lda + c0, lda, B + c0 * ldb, ldb,
                                             B + r1 * ldb, ldb, 0u, 0u, sh);
   }
-  for (int64_t c1 = n; c1 > 0; c1 -= kSub) {
-    const int64_t c0 = c1 - kSub > 0 ? c1 - kSub : 0;
+  for (int64_t c1 = n; c1 > 0; c1 -= sub) {
+    const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
     for (int64_t c = c1 - 1; c >= c0; --c) {
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
       __syncthreads();
@@ -402,6 +407,7 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
 // ---- the persistent kernel ------------------------------------------------------
 
 struct Batch {
+  Tuning tune;
   int32_t count;
   int32_t max_n;
   int32_t nb;
@@ -431,6 +437,9 @@ __global__ void __launch_bounds__(kBT, 2) vbatched_kernel(Batch bt) {
     const int64_t nrhs = SOLVE ? bt.nrhs[idx] : 0;
     uint32_t* B = SOLVE ? bt.B[idx] : nullptr;
     const int64_t ldb = SOLVE ? bt.ldb[idx] : 1;
+    int b = 0;                                   // size bucket of this system
+    while (b + 1 < bt.tune.buckets && n > bt.tune.max_n[b]) ++b;
+    const int sub = bt.tune.sub[b];
     int32_t status = 0;
     if (n < 0 || n > bt.max_n) status = -1;
     else if (n > 0 && A == nullptr) status = -2;
@@ -440,12 +449,12 @@ __global__ void __launch_bounds__(kBT, 2) vbatched_kernel(Batch bt) {
     else if (SOLVE && n > 0 && nrhs > 0 && B == nullptr) status = -6;
     else if (SOLVE && ldb < (nrhs > 1 ? nrhs : 1)) status = -7;
     if (status == 0 && FACTOR) {
-      if (KIND == 0) lu_factor(A, lda, n, bt.nb, ipiv, status, sh);
-      else chol_factor(A, lda, n, bt.nb, status, sh);
+      if (KIND == 0) lu_factor(A, lda, n, bt.nb, sub, ipiv, status, sh);
+      else chol_factor(A, lda, n, bt.nb, sub, status, sh);
     }
     if (SOLVE && status == 0 && n > 0 && nrhs > 0) {
-      if (KIND == 0) lu_solve(A, lda, n, ipiv, B, ldb, nrhs, sh);
-      else chol_solve(A, lda, n, B, ldb, nrhs, sh);
+      if (KIND == 0) lu_solve(A, lda, n, sub, ipiv, B, ldb, nrhs, sh);
+      else chol_solve(A, lda, n, sub, B, ldb, nrhs, sh);
     }
     if (threadIdx.x == 0) bt.info[idx] = status;
     __syncthreads();
@@ -468,12 +477,29 @@ int launch_kernel(hipStream_t s, const Batch& bt) {
 
 }  // namespace
 
+// Built-in sub-panel widths per size bucket, measured on MI355X (the
+// autotuner replaces them per device): a width >= n runs small systems
+// unblocked, 16 suits the LU of larger ones, 32 the larger Cholesky ones.
+Tuning default_tuning(int kind) {
+  Tuning t{};
+  t.buckets = 5;
+  const int32_t max_n[5] = {31, 63, 127, 255, 0x7FFFFFFF};
+  const int32_t lu[5] = {32, 64, 16, 16, 16};
+  const int32_t chol[5] = {32, 64, 16, 32, 32};
+  for (int b = 0; b < 5; ++b) {
+    t.max_n[b] = max_n[b];
+    t.sub[b] = kind == 0 ? lu[b] : chol[b];
+  }
+  return t;
+}
+
 int launch_vbatched(hipStream_t s, int kind, bool factor, bool solve, int32_t count, int32_t max_n,
                     int64_t nb, const int32_t* n, uint32_t* const* A, const int64_t* lda,
                     int32_t* const* ipiv, const int32_t* nrhs, uint32_t* const* B, const int64_t* ldb,
-                    int32_t* info) {
+                    int32_t* info, const Tuning* tune) {
   if (count == 0) return 0;
-  Batch bt{count, max_n, (int32_t)nb, n, A, lda, ipiv, nrhs, B, ldb, info};
+  Batch bt{tune != nullptr ? *tune : default_tuning(kind), count, max_n, (int32_t)nb, n, A, lda, ipiv, nrhs,
+           B, ldb, info};
   if (kind == 0) {
     if (factor && solve) return launch_kernel<0, true, true>(s, bt);
     if (factor) return launch_kernel<0, true, false>(s, bt);

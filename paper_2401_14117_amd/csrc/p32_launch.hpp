@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "posit32.h"
+
 namespace p32 {
 
 // Status of the most recent launch as a library return code.
@@ -36,10 +38,23 @@ int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
 int launch_potrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint32_t* B,
                  int64_t ldb);
 
-// variable-size batch: kind 0 LU, 1 Cholesky; factor and/or solve phases
+// Sub-panel width per size bucket of the batched kernels: a system of order
+// n uses sub[b] for the first bucket b with n <= max_n[b] (else the last).
+constexpr int kTuneBuckets = 8;
+struct Tuning {
+  int32_t buckets;                 // 1 .. kTuneBuckets
+  int32_t max_n[kTuneBuckets];     // ascending
+  int32_t sub[kTuneBuckets];       // 1 .. 64
+};
+Tuning default_tuning(int kind);
+// validated copy of a table of the C ABI; -1 if it is invalid
+int tuning_from_abi(const posit32_vbatch_tuning& t, Tuning* out);
+
+// variable-size batch: kind 0 LU, 1 Cholesky; factor and/or solve phases;
+// tune == nullptr takes default_tuning(kind)
 int launch_vbatched(hipStream_t s, int kind, bool factor, bool solve, int32_t count, int32_t max_n,
                     int64_t nb, const int32_t* n, uint32_t* const* A, const int64_t* lda,
                     int32_t* const* ipiv, const int32_t* nrhs, uint32_t* const* B, const int64_t* ldb,
-                    int32_t* info);
+                    int32_t* info, const Tuning* tune = nullptr);
 
 }  // namespace p32

@@ -134,6 +134,7 @@ struct Slot {
 
 struct posit32_queue {
   posit32_queue_cfg cfg{};
+  p32::Tuning tune[2];                       // sub-panel tables: LU, Cholesky
   int device = 0;
   hipStream_t compute = nullptr, copy = nullptr;
   char* dev_pool = nullptr;
@@ -248,9 +249,9 @@ int launch_batch(posit32_queue* q, Slot& s, const std::vector<Req*>& group, int 
   int32_t* info = (int32_t*)(s.dev_meta + info_off);
   if (factor)
     return p32::launch_vbatched(q->compute, kind, true, true, count, max_n, q->cfg.nb, n, A, lda,
-                                kind == 0 ? ipiv : nullptr, nrhs, B, ldb, info);
+                                kind == 0 ? ipiv : nullptr, nrhs, B, ldb, info, &q->tune[kind]);
   return p32::launch_vbatched(q->compute, kind, false, true, count, max_n, q->cfg.nb, n, A, lda,
-                              kind == 0 ? ipiv : nullptr, nrhs, B, ldb, info);
+                              kind == 0 ? ipiv : nullptr, nrhs, B, ldb, info, &q->tune[kind]);
 }
 
 // Stage, copy and launch one batch into slot s (without the lock).
@@ -499,7 +500,12 @@ int posit32_queue_create(const posit32_queue_cfg* cfg, posit32_queue** out) {
   if (cfg->nb < 1 || cfg->nb > 256) return -1;
   if (cfg->batch_max_n < 0) return -1;
   auto q = std::make_unique<posit32_queue>();
+  for (int kind = 0; kind < 2; ++kind) {
+    if (cfg->tuning == nullptr) q->tune[kind] = p32::default_tuning(kind);
+    else if (p32::tuning_from_abi(cfg->tuning[kind], &q->tune[kind])) return -1;
+  }
   q->cfg = *cfg;
+  q->cfg.tuning = nullptr;                   // the tables were copied
   q->t0 = std::chrono::steady_clock::now();
   int rc = hip_code(hipGetDevice(&q->device));
   if (!rc) rc = hip_code(hipStreamCreateWithFlags(&q->compute, hipStreamNonBlocking));

@@ -34,9 +34,44 @@ class Posit32Error(RuntimeError):
     pass
 
 
+TUNE_BUCKETS = 8
+
+
+class Tuning(ctypes.Structure):
+    """posit32_vbatch_tuning: the sub-panel width of the batched kernels per
+    size bucket (a system of order n takes sub[b] of the first bucket with
+    n <= max_n[b]).  Any table gives the same result bits."""
+    _fields_ = [("buckets", ctypes.c_int32), ("max_n", ctypes.c_int32 * TUNE_BUCKETS),
+                ("sub", ctypes.c_int32 * TUNE_BUCKETS)]
+
+    @classmethod
+    def make(cls, max_n, sub) -> "Tuning":
+        if len(max_n) != len(sub) or not 1 <= len(sub) <= TUNE_BUCKETS:
+            raise ValueError("max_n and sub need the same length, 1..8")
+        t = cls()
+        t.buckets = len(sub)
+        for b, (m, w) in enumerate(zip(max_n, sub)):
+            t.max_n[b] = int(m)
+            t.sub[b] = int(w)
+        return t
+
+    def to_dict(self) -> dict:
+        return {"max_n": list(self.max_n)[:self.buckets], "sub": list(self.sub)[:self.buckets]}
+
+
+class VBatchDesc(ctypes.Structure):
+    """posit32_vbatch: descriptor of one call of posit32_vbatched."""
+    _fields_ = [("kind", ctypes.c_int32), ("factor", ctypes.c_int32), ("solve", ctypes.c_int32),
+                ("count", ctypes.c_int32), ("max_n", ctypes.c_int32), ("nb", ctypes.c_int64),
+                ("n", ctypes.c_void_p), ("nrhs", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_void_p), ("ipiv", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("ldb", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
 class QueueCfg(ctypes.Structure):
     _fields_ = [("device_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
-                ("nb", ctypes.c_int32), ("batch_max_n", ctypes.c_int32)]
+                ("nb", ctypes.c_int32), ("batch_max_n", ctypes.c_int32),
+                ("tuning", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -85,6 +120,10 @@ def lib() -> ctypes.CDLL:
     L.posit32_potrf_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
     L.posit32_potrs_vbatched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.posit32_posv_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_vbatched.argtypes = [vp, ctypes.POINTER(VBatchDesc), ctypes.POINTER(Tuning)]
+    L.posit32_vbatched.restype = i32
+    L.posit32_vbatched_default_tuning.argtypes = [i32, ctypes.POINTER(Tuning)]
+    L.posit32_vbatched_default_tuning.restype = i32
     L.posit32_queue_create.argtypes = [ctypes.POINTER(QueueCfg), ctypes.POINTER(ctypes.c_void_p)]
     L.posit32_queue_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.posit32_queue_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Result)]
@@ -109,6 +148,59 @@ def _check(rc: int, what: str) -> None:
     if rc != 0:
         msg = lib().posit32_strerror(rc).decode()
         raise Posit32Error(f"{what} failed with code {rc}: {msg}")
+
+
+KIND_CODES = {"lu": 0, "chol": 1}
+_tunings: dict | None = None
+TUNING_DIR = os.path.join(HERE, "tuning")
+
+
+def default_tuning(kind: str) -> Tuning:
+    """The library's built-in sub-panel table for kind "lu" or "chol"."""
+    t = Tuning()
+    _check(lib().posit32_vbatched_default_tuning(KIND_CODES[kind], ctypes.byref(t)),
+           "posit32_vbatched_default_tuning")
+    return t
+
+
+def tuning_file() -> str | None:
+    """The tuning file in use: $POSIT32_TUNING (a path, or "builtin" for
+    none), else tuning/<arch>.json beside this module if it exists (written by
+    paper_2401_14117_amd.autotune for the current GPU)."""
+    env = os.environ.get("POSIT32_TUNING")
+    if env:
+        return None if env == "builtin" else env
+    if not torch.cuda.is_available():
+        return None
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = os.path.join(TUNING_DIR, f"{arch}.json")
+    return path if os.path.exists(path) else None
+
+
+def active_tuning(kind: str) -> Tuning | None:
+    """The measured table for kind from tuning_file(), or None (the library's
+    built-in table)."""
+    global _tunings
+    if _tunings is None:
+        _tunings = {}
+        path = tuning_file()
+        if path is not None:
+            import json
+            with open(path) as f:
+                data = json.load(f)
+            for k in KIND_CODES:
+                if k in data:
+                    _tunings[k] = Tuning.make(data[k]["max_n"], data[k]["sub"])
+    return _tunings.get(kind)
+
+
+def set_active_tuning(kind: str, tuning: Tuning | None) -> None:
+    """Replace the table used by VBatch and Queue for kind (None: built-in)."""
+    active_tuning(kind)
+    if tuning is None:
+        _tunings.pop(kind, None)
+    else:
+        _tunings[kind] = tuning
 
 
 def _stream(stream) -> int:
@@ -300,47 +392,80 @@ class VBatch:
         if self.ipiv is None:
             raise ValueError("this batch was built without pivot vectors (lu=False)")
 
-    def getrf(self, nb: int = 256, stream=None) -> torch.Tensor:
+    def run(self, factor: bool, solve: bool, nb: int = 256, tuning=None, stream=None) -> torch.Tensor:
+        """One posit32_vbatched call: factor and/or solve every system with the
+        sub-panel table `tuning` (a Tuning; None: active_tuning() of this
+        batch's kind, else the library's built-in table)."""
+        kind = "lu" if self.ipiv is not None else "chol"
+        if solve:
+            self._need_b()
+        if tuning is None:
+            tuning = active_tuning(kind)
+        d = VBatchDesc(KIND_CODES[kind], int(factor), int(solve), self.count, self.max_n, nb,
+                       _ptr(self.n), _ptr(self.nrhs) if solve else None, _ptr(self.A), _ptr(self.lda),
+                       _ptr(self.ipiv), _ptr(self.B) if solve else None, _ptr(self.ldb) if solve else None,
+                       _ptr(self.info))
+        _check(lib().posit32_vbatched(_stream(stream), ctypes.byref(d),
+                                      None if tuning is None else ctypes.byref(tuning)),
+               "posit32_vbatched")
+        return self.info
+
+    # The six calls below go through posit32_vbatched with the active tuning
+    # table unless tuned=False, which calls the dedicated entry points (the
+    # library's built-in table).  The results are the same bits either way.
+    def getrf(self, nb: int = 256, stream=None, tuned: bool = True) -> torch.Tensor:
         self._need_piv()
+        if tuned:
+            return self.run(True, False, nb, stream=stream)
         _check(lib().posit32_getrf_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
                                             _ptr(self.A), _ptr(self.lda), _ptr(self.ipiv),
                                             _ptr(self.info)), "posit32_getrf_vbatched")
         return self.info
 
-    def getrs(self, stream=None) -> torch.Tensor:
+    def getrs(self, stream=None, tuned: bool = True) -> torch.Tensor:
         self._need_piv()
         self._need_b()
+        if tuned:
+            return self.run(False, True, stream=stream)
         _check(lib().posit32_getrs_vbatched(_stream(stream), self.count, self.max_n, _ptr(self.n),
                                             _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
                                             _ptr(self.ipiv), _ptr(self.B), _ptr(self.ldb),
                                             _ptr(self.info)), "posit32_getrs_vbatched")
         return self.info
 
-    def gesv(self, nb: int = 256, stream=None) -> torch.Tensor:
+    def gesv(self, nb: int = 256, stream=None, tuned: bool = True) -> torch.Tensor:
         self._need_piv()
         self._need_b()
+        if tuned:
+            return self.run(True, True, nb, stream=stream)
         _check(lib().posit32_gesv_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
                                            _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
                                            _ptr(self.ipiv), _ptr(self.B), _ptr(self.ldb),
                                            _ptr(self.info)), "posit32_gesv_vbatched")
         return self.info
 
-    def potrf(self, nb: int = 256, stream=None) -> torch.Tensor:
+    def potrf(self, nb: int = 256, stream=None, tuned: bool = True) -> torch.Tensor:
+        if tuned:
+            return self.run(True, False, nb, stream=stream)
         _check(lib().posit32_potrf_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
                                             _ptr(self.A), _ptr(self.lda), _ptr(self.info)),
                "posit32_potrf_vbatched")
         return self.info
 
-    def potrs(self, stream=None) -> torch.Tensor:
+    def potrs(self, stream=None, tuned: bool = True) -> torch.Tensor:
         self._need_b()
+        if tuned:
+            return self.run(False, True, stream=stream)
         _check(lib().posit32_potrs_vbatched(_stream(stream), self.count, self.max_n, _ptr(self.n),
                                             _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
                                             _ptr(self.B), _ptr(self.ldb), _ptr(self.info)),
                "posit32_potrs_vbatched")
         return self.info
 
-    def posv(self, nb: int = 256, stream=None) -> torch.Tensor:
+    def posv(self, nb: int = 256, stream=None, tuned: bool = True) -> torch.Tensor:
         self._need_b()
+        if tuned:
+            return self.run(True, True, nb, stream=stream)
         _check(lib().posit32_posv_vbatched(_stream(stream), self.count, self.max_n, nb, _ptr(self.n),
                                            _ptr(self.nrhs), _ptr(self.A), _ptr(self.lda),
                                            _ptr(self.B), _ptr(self.ldb), _ptr(self.info)),
@@ -356,7 +481,12 @@ class Queue:
     def __init__(self, device_bytes: int = 2 << 30, max_batch: int = 1024, nb: int = 256,
                  batch_max_n: int = 512):
         import numpy as np  # noqa: F401
-        cfg = QueueCfg(device_bytes, max_batch, nb, batch_max_n)
+        tl, tc = active_tuning("lu"), active_tuning("chol")
+        self._tunings = None
+        if tl is not None or tc is not None:
+            self._tunings = (Tuning * 2)(tl or default_tuning("lu"), tc or default_tuning("chol"))
+        cfg = QueueCfg(device_bytes, max_batch, nb, batch_max_n,
+                       ctypes.addressof(self._tunings) if self._tunings is not None else None)
         h = ctypes.c_void_p()
         _check(lib().posit32_queue_create(ctypes.byref(cfg), ctypes.byref(h)), "posit32_queue_create")
         self._h = h

@@ -120,3 +120,51 @@ def test_queue_argument_errors(L):
     assert L.posit32_factor_release(None, 1) == -1
     assert L.posit32_queue_destroy(None) == -1
     assert L.posit32_strerror(-4000) == b"the system does not fit the queue's device pool"
+
+
+def test_vbatched_descriptor_and_tuning_validation(L):
+    """posit32_vbatched checks its descriptor and table on the host (nothing
+    is dereferenced or launched when they are invalid)."""
+    import ctypes
+    from paper_2401_14117_amd import posit32 as P
+    ok = dict(kind=0, factor=1, solve=1, count=4, max_n=10, nb=256, n=8, nrhs=8, A=8, lda=8, ipiv=8,
+              B=8, ldb=8, info=8)
+
+    def desc(**kw):
+        d = dict(ok)
+        d.update(kw)
+        return P.VBatchDesc(*[d[f] for f, _ in P.VBatchDesc._fields_])
+
+    def call(d, t=None):
+        return L.posit32_vbatched(None, None if d is None else ctypes.byref(d),
+                                  None if t is None else ctypes.byref(t))
+
+    assert call(None) == -2
+    for bad in (dict(kind=2), dict(factor=0, solve=0), dict(factor=2), dict(count=-1), dict(max_n=-1),
+                dict(nb=0), dict(nb=257), dict(n=None), dict(ipiv=None), dict(nrhs=None), dict(B=None),
+                dict(info=None)):
+        assert call(desc(**bad)) == -2, bad
+    big = 2**31 - 1
+    for t in (P.Tuning.make([big], [0]), P.Tuning.make([big], [65]), P.Tuning.make([50, 50], [8, 8]),
+              P.Tuning.make([50, 20], [8, 8])):
+        assert call(desc(), t) == -3, t.to_dict()
+    t = P.Tuning()
+    t.buckets = 9
+    assert call(desc(), t) == -3
+    t.buckets = 0
+    assert call(desc(), t) == -3
+    # an empty batch is valid and launches nothing
+    assert call(desc(count=0, n=None, A=None, lda=None, ipiv=None, nrhs=None, B=None, ldb=None,
+                     info=None), P.Tuning.make([big], [16])) == 0
+
+
+def test_default_tuning_tables(L):
+    from paper_2401_14117_amd import posit32 as P
+    for kind in ("lu", "chol"):
+        t = P.default_tuning(kind)
+        assert 1 <= t.buckets <= P.TUNE_BUCKETS
+        mx = list(t.max_n)[:t.buckets]
+        assert mx == sorted(mx) and len(set(mx)) == len(mx) and mx[-1] == 2**31 - 1
+        assert all(1 <= s <= 64 for s in list(t.sub)[:t.buckets])
+    assert L.posit32_vbatched_default_tuning(2, None) == -1
+    assert L.posit32_vbatched_default_tuning(0, None) == -2

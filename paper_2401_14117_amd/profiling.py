@@ -137,8 +137,65 @@ def kernel_table(args) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def valu_table(args) -> None:
+    """VALU utilisation of the Rgemm kernel from one SQ counter pass: VALU
+    instructions per multiply-add and the issue rate against the chip's
+    integer-VALU peaks (256 CUs x 2.4 GHz x 128 or 64 lanes per clock)."""
+    stats = kernel_stats(args.trace)
+    name = next(k for k in stats if args.kernel in k)
+    avg_ns = stats[name][1]
+    m, n, k = args.mnk
+    madds = float(m) * n * k
+    ctr = {c: counter_per_dispatch(args.pmc, c, args.kernel) for c in args.counters}
+    cycles = avg_ns * 1e-9 * args.clock_ghz * 1e9
+    lines = [f"# rocprofv3: VALU utilisation of the Posit(32,2) Rgemm kernel, {args.workload}", "",
+             f"Kernel: `{name}`", f"Kernel source hash: {args.kernel_hash}.", "",
+             "Commands (run on the MI355X box from /tmp, REPO = the repository root):", "", "```",
+             f"rocprofv3 --pmc {' '.join(args.counters)} --kernel-trace --output-format csv "
+             f"-d $REPO/gpurun_out/prof/valu -o valu -- python3 $REPO/bench.py --workload {args.workload} "
+             "--steps 1 --warmup 0 --cpu-budget 0",
+             "(kernel duration from the --kernel-trace --stats run of the Rgemm summary)", "```", "",
+             "| counter (per dispatch, summed over the chip) | value |", "|---|---|"]
+    for c in args.counters:
+        lines.append(f"| {c} | {ctr[c]:.4g} |")
+    lines += ["", "| derived | value |", "|---|---|",
+              f"| average kernel duration (trace) | {avg_ns / 1e6:.3f} ms |"]
+    if "SQ_INSTS_VALU" in ctr:
+        lane = ctr["SQ_INSTS_VALU"] * 64.0
+        rate = lane / (avg_ns * 1e-9)
+        per_cu = ctr["SQ_INSTS_VALU"] / args.cus / cycles
+        lines += [f"| VALU lane-instructions per multiply-add (whole kernel) | {lane / madds:.2f} |",
+                  f"| VALU issue rate | {rate / 1e12:.2f} T lane-instr/s |",
+                  f"| of the 128-lane/clk/CU peak ({args.cus * 128 * args.clock_ghz / 1e3:.1f} T) | "
+                  f"{rate / (args.cus * 128 * args.clock_ghz * 1e9):.1%} |",
+                  f"| of the 64-lane/clk/CU rate ({args.cus * 64 * args.clock_ghz / 1e3:.1f} T) | "
+                  f"{rate / (args.cus * 64 * args.clock_ghz * 1e9):.1%} |",
+                  f"| wave-instructions per CU per clock | {per_cu:.3f} |"]
+    if "SQ_INSTS_LDS" in ctr:
+        lines.append(f"| LDS instructions per multiply-add (per 64 lanes) | {ctr['SQ_INSTS_LDS'] * 64 / madds:.3f} |")
+    if "SQ_INSTS_SALU" in ctr:
+        lines.append(f"| SALU instructions per multiply-add (per 64 lanes) | {ctr['SQ_INSTS_SALU'] * 64 / madds:.3f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main() -> None:
     import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "valu":
+        ap = argparse.ArgumentParser(description=valu_table.__doc__)
+        ap.add_argument("mode")
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--pmc", required=True)
+        ap.add_argument("--counters", nargs="+", required=True)
+        ap.add_argument("--kernel", default="gemm_kernel<false, false, false, false>")
+        ap.add_argument("--workload", default="square_n8192")
+        ap.add_argument("--mnk", type=int, nargs=3, default=[8192, 8192, 8192])
+        ap.add_argument("--cus", type=int, default=256)
+        ap.add_argument("--clock-ghz", type=float, default=2.4)
+        ap.add_argument("--kernel-hash", required=True)
+        ap.add_argument("--out", required=True)
+        valu_table(ap.parse_args())
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":
         ap = argparse.ArgumentParser(description=kernel_table.__doc__)
         ap.add_argument("mode")

@@ -177,6 +177,15 @@ __device__ __forceinline__ win add_unchecked(win a, win b, const lut_t* __restri
   return w;
 }
 
+// A workgroup-uniform 64-bit value, passed through readfirstlane so that the
+// compiler keeps it in scalar registers and does not fold it into per-thread
+// addresses that would then stay live across the k loop.
+__device__ __forceinline__ int64_t uniform64(int64_t u) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // One k step for the thread's TM x TN accumulators.  Flagged lanes redo the
 // whole step on the exact path.
 template <bool CHECKED>
@@ -276,20 +285,43 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
       }
     }
 
+  // Staging addresses.  Element l of this thread's share of a k-tile sits at
+  // a workgroup-uniform offset (a function of l and p0, kept in scalar
+  // registers) plus a per-thread offset that is the same for every l and
+  // every k-tile, so the k loop carries one 64-bit offset per operand
+  // instead of one pointer per staged element.
+  static_assert(NT % BK == 0 && NT % BM == 0 && NT % BN == 0, "staging layout");
+  const int a_r = TA ? tid / BM : tid / BK;     // stored row of A within the l-group
+  const int a_c = TA ? tid % BM : tid % BK;     // stored column
+  const int b_r = TB ? tid / BK : tid / BN;
+  const int b_c = TB ? tid % BK : tid % BN;
+  const int64_t a_off = (int64_t)a_r * lda + a_c;
+  const int64_t b_off = (int64_t)b_r * ldb + b_c;
+
+  // rows of op(A) and columns of op(B) left in this tile (clamped: a tile
+  // index is below 64), compared with 32-bit per-thread indices
+  const int rem_m = (int)min(m - i0, (int64_t)BM), rem_n = (int)min(n - j0, (int64_t)BN);
+
   for (int64_t p0 = 0; p0 < k; p0 += BK) {
     int my_ok = 1;
+    const int rem_k = (int)min(k - p0, (int64_t)BK);
     __syncthreads();
 #pragma unroll
     for (int l = 0; l < (BM * BK) / NT; ++l) {
-      const int idx = tid + l * NT;
-      const int ii = TA ? idx % BM : idx / BK;
-      const int pp = TA ? idx / BM : idx % BK;
-      const int64_t gi = i0 + ii, gp = p0 + pp;
-      const int64_t gk = REVK ? k - 1 - gp : gp;
+      // op(A)(i0 + ii, p0 + pp) with ii, pp this thread's element l
+      const int ii = TA ? a_c : a_r + l * (NT / BK);
+      const int pp = TA ? a_r + l * (NT / BM) : a_c;
       uint32_t v;
-      if (gp >= k) v = 0u;
-      else if (gi >= m) v = kOne;
-      else v = TA ? A[gk * lda + gi] : A[gi * lda + gk];
+      if (pp >= rem_k) v = 0u;
+      else if (ii >= rem_m) v = kOne;
+      else if (REVK) {
+        const int64_t gi = i0 + ii, gk = k - 1 - (p0 + pp);
+        v = TA ? A[gk * lda + gi] : A[gi * lda + gk];
+      }
+      else {
+        const int64_t u = TA ? (p0 + l * (NT / BM)) * lda + i0 : (i0 + l * (NT / BK)) * lda + p0;
+        v = A[uniform64(u) + a_off];
+      }
       if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
       const dec d = decode(v);
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
@@ -297,15 +329,20 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
     }
 #pragma unroll
     for (int l = 0; l < (BN * BK) / NT; ++l) {
-      const int idx = tid + l * NT;
-      const int jj = TB ? idx / BK : idx % BN;
-      const int pp = TB ? idx % BK : idx / BN;
-      const int64_t gj = j0 + jj, gp = p0 + pp;
-      const int64_t gk = REVK ? k - 1 - gp : gp;
+      // op(B)(p0 + pp, j0 + jj)
+      const int jj = TB ? b_r + l * (NT / BK) : b_c;
+      const int pp = TB ? b_c : b_r + l * (NT / BN);
       uint32_t v;
-      if (gp >= k) v = 0u;
-      else if (gj >= n) v = kOne;
-      else v = TB ? B[gj * ldb + gk] : B[gk * ldb + gj];
+      if (pp >= rem_k) v = 0u;
+      else if (jj >= rem_n) v = kOne;
+      else if (REVK) {
+        const int64_t gj = j0 + jj, gk = k - 1 - (p0 + pp);
+        v = TB ? B[gj * ldb + gk] : B[gk * ldb + gj];
+      }
+      else {
+        const int64_t u = TB ? (j0 + l * (NT / BK)) * ldb + p0 : (p0 + l * (NT / BN)) * ldb + j0;
+        v = B[uniform64(u) + b_off];
+      }
       if (v == kNaR) { colNaR[jj] = 1; v = kOne; }
       const dec d = decode(v);
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);

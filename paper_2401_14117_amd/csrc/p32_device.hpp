@@ -411,6 +411,46 @@ __device__ inline uint32_t encode_win(win w) {
   return neg ? 0u - p : p;
 }
 
+// decoded form of a window-form value (exactly a posit): |s| in [2^27, 2^28)
+__device__ __forceinline__ dec dec_of_win(win w) {
+  dec d;
+  const bool big = w.h >= (1 << 28) || w.h <= -(1 << 28);   // a power of two held one bit high
+  d.s = big ? (w.h >> 1) : w.h;
+  d.sc = w.h == 0 ? kEZero : (big ? w.e + 1 : w.e);
+  return d;
+}
+
+// rnd(a / b) in window form for decoded a, b (b nonzero, neither NaR), with
+// rcp_b = 1.0 / |b.s| computed beforehand (a divisor reused along a chain
+// costs one binary64 multiply per quotient).  The estimate num * rcp_b is
+// within one unit of the 37-bit integer quotient, which is then fixed up
+// exactly in integers; the remainder is the sticky bit.
+__device__ inline win div_win(dec a, dec b, double rcp_b) {
+  win w;
+  if (a.s == 0) {
+    w.h = 0;
+    w.e = kEZero;
+    return w;
+  }
+  const bool neg = (a.s < 0) != (b.s < 0);
+  const uint64_t ma = (uint64_t)(a.s < 0 ? -(int64_t)a.s : a.s);
+  const uint64_t mb = (uint64_t)(b.s < 0 ? -(int64_t)b.s : b.s);
+  const uint64_t num = ma << 36;                 // 28 significant bits: exact in binary64
+  uint64_t q = (uint64_t)((double)num * rcp_b);
+  int64_t r = (int64_t)(num - q * mb);
+  if (r < 0) { q -= 1; r += (int64_t)mb; }
+  else if (r >= (int64_t)mb) { q += 1; r -= (int64_t)mb; }
+  const int L = 63 - __clzll(q);                 // 35 or 36: q in [2^35, 2^37)
+  const int sc = a.sc - b.sc - 36 + L;
+  if (scale_ok(sc)) {
+    const uint64_t qn = q << (60 - L);           // leading bit at 60
+    const uint32_t hi = (uint32_t)(qn >> 32), lo = (uint32_t)qn;
+    const int32_t h2 = (int32_t)(2u * hi + (uint32_t)((lo != 0u) | (r != 0)));
+    return round_h2(neg ? -h2 : h2, sc);         // round to nearest even is odd-symmetric
+  }
+  return win_of(round_general64(neg, q, a.sc - b.sc - 36, r != 0));
+}
+
 // rnd(x * y) in window form, fast path with exact fallback
 __device__ inline win mul_win(dec x, dec y) {
   win r;

@@ -1,7 +1,8 @@
 // p32_elementwise.hip -- conversions and elementwise Posit(32,2) arithmetic
-// (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2): add and multiply take
-// the window-form fast path with the exact routines as fallback, divide and
-// square root the exact routines.  Grid-stride loops; every element
+// (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2): add, multiply and
+// divide take the window-form fast path with the exact routines as fallback
+// (the quotient from a binary64 estimate fixed up exactly in integers),
+// square root the exact routine.  Grid-stride loops; every element
 // independent.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -71,9 +72,12 @@ __global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict
       case 2:
         r = (xn || yn) ? kNaR : encode_win(mul_win(decode(x), decode(y)));
         break;
-      case 3:
-        r = div_general(decode(x), decode(y), xn, yn);
+      case 3: {
+        const dec dx = decode(x), dy = decode(y);
+        if (xn || yn || dy.s == 0) r = kNaR;         // x / 0 = NaR
+        else r = encode_win(div_win(dx, dy, 1.0 / (double)(dy.s < 0 ? -(int64_t)dy.s : (int64_t)dy.s)));
         break;
+      }
       default:
         r = sqrt_general(decode(x), xn);
         break;

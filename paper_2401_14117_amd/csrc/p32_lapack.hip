@@ -481,51 +481,70 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
 // Diagonal block [s, s+bs) (bs <= kTrsvBlock = 64) of the solve for one
 // right-hand side q: one wave per right-hand side, lane r owns row s + r and
 // keeps it decoded (window form plus a NaR flag).  The block's coefficients
-// are staged in LDS once; then, per column c in solve order, the owner lane
-// of row c (final once its own last update is in) divides it by the diagonal
-// (non-unit kinds) and broadcasts it with a wave shuffle, and every later row
-// r gets x[r] - rnd(T(r,c) x[c]).  No barrier inside the chain.
+// are staged in LDS once, already decoded, and each lane holds its own
+// diagonal entry with a binary64 reciprocal for the quotient estimate.  Per
+// column c in solve order, the owner lane of row c (final once its own last
+// update is in) divides it by the diagonal (non-unit kinds); the quotient is
+// read by every lane with v_readlane (the column index is wave-uniform), and
+// every later row r gets x[r] - rnd(T(r,c) x[c]).  No barrier or LDS access
+// on the chain itself.
 constexpr int kTrsvBlock = 64;
+constexpr int32_t kScNaR = 1 << 20;              // scale field of a staged NaR coefficient
 
 __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
                  int64_t nrhs, int64_t s, int bs, int kind) {
-  __shared__ uint32_t coef[kTrsvBlock][kTrsvBlock + 1];
-  __shared__ uint32_t diag[kTrsvBlock];
+  __shared__ int2 coef[kTrsvBlock][kTrsvBlock + 1];
   const bool forward = kind == 0 || kind == 2;
   const bool unit = kind == 0;
   const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
-  if (!unit && lane < bs) diag[lane] = M[(s + lane) * lda + s + lane];
-  // coef[r][u]: coefficient of the u-th column in solve order in row r
+  // coef[r][u]: coefficient of the u-th column in solve order in row r, decoded
   for (int idx = lane; idx < bs * bs; idx += kTrsvBlock) {
     int r, u;
     if (kind == 3) { u = idx / bs; r = idx - u * bs; }     // row c of M is contiguous in r
     else { r = idx / bs; u = idx - r * bs; }
     const int64_t c = forward ? s + u : s + bs - 1 - u;
-    coef[r][u] = tri_coef(M, lda, kind, s + r, c);
+    const uint32_t m = tri_coef(M, lda, kind, s + r, c);
+    const dec d = decode(m);
+    coef[r][u] = make_int2(d.s, m == kNaR ? kScNaR : d.sc);
+  }
+  // this lane's diagonal entry (the divisor when it owns the column)
+  dec dg;
+  dg.s = 0;
+  dg.sc = kEZero;
+  bool dg_bad = true;                            // NaR or zero: quotients are NaR
+  double rcp = 0.0;
+  if (!unit && lane < bs) {
+    const uint32_t dp = M[(s + lane) * lda + s + lane];
+    dg = decode(dp);
+    dg_bad = dp == kNaR || dg.s == 0;
+    if (!dg_bad) rcp = 1.0 / (double)(dg.s < 0 ? -(int64_t)dg.s : (int64_t)dg.s);
   }
   const uint32_t x0 = lane < bs ? B[(s + lane) * ldb + q] : 0u;
   bool xnar = x0 == kNaR;
   win x = win_of(xnar ? 0u : x0);
   __syncthreads();
   for (int u = 0; u < bs; ++u) {
-    const int cl = forward ? u : bs - 1 - u;                // local column
-    uint32_t pc = 0u;
-    if (lane == cl) {
-      pc = xnar ? kNaR : encode_win(x);
-      if (!unit) {
-        pc = p_div(pc, diag[cl]);
-        xnar = pc == kNaR;
-        x = win_of(xnar ? 0u : pc);
-      }
+    const int cl = forward ? u : bs - 1 - u;                // local column (wave-uniform)
+    if (!unit && lane == cl) {
+      if (dg_bad) xnar = true;
+      else if (!xnar) x = div_win(dec_of_win(x), dg, rcp);
     }
-    pc = __shfl(pc, cl);
+    win pc;
+    pc.h = __builtin_amdgcn_readlane(x.h, cl);
+    pc.e = __builtin_amdgcn_readlane(x.e, cl);
+    const bool pnar = __builtin_amdgcn_readlane((int)xnar, cl) != 0;
     const bool below = forward ? lane > cl : lane < cl;
     if (lane < bs && below) {
-      const uint32_t m = coef[lane][u];
-      if (m == kNaR || pc == kNaR) xnar = true;
-      else if (!xnar) x = fms_win(x, decode(m), decode(pc));
+      const int2 m = coef[lane][u];
+      if (m.y == kScNaR || pnar) xnar = true;
+      else if (!xnar) {
+        dec md;
+        md.s = m.x;
+        md.sc = m.y;
+        x = fms_win(x, md, dec_of_win(pc));
+      }
     }
   }
   if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(x);

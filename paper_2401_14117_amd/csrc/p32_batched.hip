@@ -137,8 +137,10 @@ __device__ __forceinline__ void lu_subpanel(uint32_t* A, int64_t lda, int64_t n,
       sh.urow[t] = u;
       sh.udec[t] = decode(u);
     }
-    if (piv != 0u)
-      for (int64_t i = c + 1 + t; i < n; i += kBT) A[i * lda + c] = p_div(A[i * lda + c], piv);
+    if (piv != 0u) {
+      const divisor pd = make_divisor(piv);
+      for (int64_t i = c + 1 + t; i < n; i += kBT) A[i * lda + c] = p_div_by(A[i * lda + c], pd);
+    }
     __syncthreads();
     const int64_t cnt = (n - c - 1) * wq;
     for (int64_t idx = t; idx < cnt; idx += kBT) {
@@ -258,7 +260,8 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
   for (int64_t c1 = n; c1 > 0; c1 -= sub) {
     const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
     for (int64_t c = c1 - 1; c >= c0; --c) {
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], LU[c * lda + c]);
+      const divisor dv = make_divisor(LU[c * lda + c]);
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
       const int64_t cnt = (c - c0) * nrhs;
       for (int64_t idx = t; idx < cnt; idx += kBT) {
@@ -291,7 +294,7 @@ __device__ __forceinline__ int64_t chol_subblock(uint32_t* A, int64_t lda, int64
     if (sh.flag) return c;
     const uint32_t d = A[c * lda + c];
     const int rows = w - cl - 1;
-    if (t < rows) A[(c + 1 + t) * lda + c] = p_div(A[(c + 1 + t) * lda + c], d);
+    if (t < rows) A[(c + 1 + t) * lda + c] = p_div_by(A[(c + 1 + t) * lda + c], make_divisor(d));
     __syncthreads();
     for (int idx = t; idx < rows * rows; idx += kBT) {
       const int a = idx / rows, b = idx - a * rows;  // element (c+1+a, c+1+b), b <= a
@@ -317,7 +320,8 @@ __device__ __forceinline__ void chol_trsm_rows(uint32_t* A, int64_t lda, int64_t
   __syncthreads();
   for (int cl = 0; cl < steps; ++cl) {
     const int64_t c = c0 + cl;
-    for (int64_t r = r0 + t; r < r1; r += kBT) A[r * lda + c] = p_div(A[r * lda + c], sh.diag[cl]);
+    const divisor dv = make_divisor(sh.diag[cl]);
+    for (int64_t r = r0 + t; r < r1; r += kBT) A[r * lda + c] = p_div_by(A[r * lda + c], dv);
     __syncthreads();
     const int wq = w - cl - 1;
     const int64_t cnt = nr * wq;
@@ -371,7 +375,8 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
     const int w = (int)(sub < n - c0 ? sub : n - c0);
     for (int cl = 0; cl < w; ++cl) {
       const int64_t c = c0 + cl;
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
+      const divisor dv = make_divisor(L[c * lda + c]);
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
       const int64_t cnt = (w - cl - 1) * nrhs;
       for (int64_t idx = t; idx < cnt; idx += kBT) {
@@ -388,7 +393,8 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
   for (int64_t c1 = n; c1 > 0; c1 -= sub) {
     const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
     for (int64_t c = c1 - 1; c >= c0; --c) {
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div(B[c * ldb + q], L[c * lda + c]);
+      const divisor dv = make_divisor(L[c * lda + c]);
+      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
       const int64_t cnt = (c - c0) * nrhs;
       for (int64_t idx = t; idx < cnt; idx += kBT) {

@@ -451,6 +451,28 @@ __device__ inline win div_win(dec a, dec b, double rcp_b) {
   return win_of(round_general64(neg, q, a.sc - b.sc - 36, r != 0));
 }
 
+// A divisor prepared once for many quotients: decoded, with its binary64
+// reciprocal; NaR and zero divisors give NaR quotients.
+struct divisor {
+  dec d;
+  double rcp;
+  bool bad;
+};
+
+__device__ __forceinline__ divisor make_divisor(uint32_t b) {
+  divisor v;
+  v.d = decode(b);
+  v.bad = b == kNaR || v.d.s == 0;
+  v.rcp = v.bad ? 0.0 : 1.0 / (double)(v.d.s < 0 ? -(int64_t)v.d.s : (int64_t)v.d.s);
+  return v;
+}
+
+// rnd(a / b) on patterns with b prepared by make_divisor
+__device__ __forceinline__ uint32_t p_div_by(uint32_t a, const divisor& b) {
+  if (a == kNaR || b.bad) return kNaR;
+  return encode_win(div_win(decode(a), b.d, b.rcp));
+}
+
 // rnd(x * y) in window form, fast path with exact fallback
 __device__ inline win mul_win(dec x, dec y) {
   win r;

@@ -251,8 +251,10 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     }
     // rows below c: scale column c
     const int rs = (int)max((int64_t)0, c + 1 - r0);
-    if (piv != 0u)
-      for (int rr = rs + t; rr < nr; rr += kPanelThreads) T[rr * ts + cl] = p_div(T[rr * ts + cl], piv);
+    if (piv != 0u) {
+      const divisor pd = make_divisor(piv);
+      for (int rr = rs + t; rr < nr; rr += kPanelThreads) T[rr * ts + cl] = p_div_by(T[rr * ts + cl], pd);
+    }
     __syncthreads();
     if (cl + 1 == jb) break;
     const int64_t c1 = c + 1;
@@ -376,6 +378,7 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
              const uint32_t* __restrict__ saved) {
   __shared__ uint32_t D[kTri];
   __shared__ uint32_t col[kMaxNB];
+  __shared__ dec cold[kMaxNB];                    // col, decoded
   __shared__ int stop;
   const int t = threadIdx.x;
   uint32_t* G = A + j * lda + j;
@@ -402,11 +405,16 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
     }
     __syncthreads();
     if (stop) break;
-    const uint32_t d = D[tri_off(c) + c];
+    // the divisor is a positive square root: one binary64 reciprocal serves
+    // the whole column's quotients
+    const dec dd = decode(D[tri_off(c) + c]);
+    const double rcp = 1.0 / (double)dd.s;
     for (int r = c + 1 + t; r < jb; r += kPotf2Threads) {
-      const uint32_t x = p_div(D[tri_off(r) + c], d);
+      const uint32_t a = D[tri_off(r) + c];
+      const uint32_t x = a == kNaR ? kNaR : encode_win(div_win(decode(a), dd, rcp));
       D[tri_off(r) + c] = x;
       col[r] = x;
+      cold[r] = decode(x);
     }
     __syncthreads();
     // trailing triangle: local row a = i-c-1, local column b = q-c-1 <= a
@@ -417,7 +425,7 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
       if (tri_off(a + 1) <= idx) ++a;
       if (tri_off(a) > idx) --a;
       const int i = c + 1 + a, q = c + 1 + (idx - tri_off(a));
-      D[tri_off(i) + q] = p_fms(D[tri_off(i) + q], col[i], col[q]);
+      D[tri_off(i) + q] = p_fms_pre(D[tri_off(i) + q], col[i], cold[i], col[q], cold[q]);
     }
     __syncthreads();
   }
@@ -429,40 +437,66 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
 // at A[j][j] (jb <= kCholTrsmMax): one wave per row, lane t holds column
 // j + t.  Column by column: x_c = A[r][c] / L[c][c] is final once the updates
 // from columns < c are in, then columns c' > c get A[r][c'] - rnd(x_c *
-// L[c'][c]).  The triangle is staged in LDS once per workgroup (four rows).
+// L[c'][c]).  The triangle is staged in LDS once per workgroup (four rows),
+// already decoded; lane c keeps L[c][c] with a binary64 reciprocal for its
+// quotient, and the new x_c reaches the other lanes through v_readlane.
 constexpr int kCholTrsmMax = 64;
+constexpr int32_t kScNaR = 1 << 20;              // scale field of a staged NaR coefficient
 
 __global__ void __launch_bounds__(256)
 trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t r_end, int64_t j,
                  int64_t jb, const int32_t* __restrict__ info) {
-  __shared__ uint32_t Ls[kCholTrsmMax][kCholTrsmMax + 1];
+  __shared__ int2 Ls[kCholTrsmMax][kCholTrsmMax + 1];   // decoded, NaR as scale kScNaR
   if (*info != 0) return;
   const int lane = threadIdx.x & 63;
   const int w = (int)jb;
   for (int idx = threadIdx.x; idx < w * w; idx += 256) {
     const int cc = idx / w, c = idx - cc * w;
-    if (c <= cc) Ls[cc][c] = A[(j + cc) * lda + j + c];
+    if (c <= cc) {
+      const uint32_t m = A[(j + cc) * lda + j + c];
+      const dec d = decode(m);
+      Ls[cc][c] = make_int2(d.s, m == kNaR ? kScNaR : d.sc);
+    }
   }
   __syncthreads();
   const int64_t r = r_begin + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= r_end) return;
   uint32_t* row = A + r * lda + j;
+  // lane c's divisor L[c][c] with its binary64 reciprocal (NaR or zero: NaR quotients)
+  dec dg;
+  dg.s = 0;
+  dg.sc = kEZero;
+  bool dg_bad = true;
+  double rcp = 0.0;
+  if (lane < w) {
+    const int2 d2 = Ls[lane][lane];
+    dg.s = d2.x;
+    dg.sc = d2.y;
+    dg_bad = d2.y == kScNaR || d2.x == 0;
+    if (!dg_bad) rcp = 1.0 / (double)(dg.s < 0 ? -(int64_t)dg.s : (int64_t)dg.s);
+  }
   // lane c's value, kept decoded (window form plus a NaR flag)
   const uint32_t v0 = lane < w ? row[lane] : 0u;
   bool vnar = v0 == kNaR;
   win v = win_of(vnar ? 0u : v0);
   for (int c = 0; c < w; ++c) {
-    uint32_t xc = 0u;
     if (lane == c) {
-      xc = p_div(vnar ? kNaR : encode_win(v), Ls[c][c]);
-      vnar = xc == kNaR;
-      v = win_of(vnar ? 0u : xc);
+      if (dg_bad) vnar = true;
+      else if (!vnar) v = div_win(dec_of_win(v), dg, rcp);
     }
-    xc = __shfl(xc, c);
+    win xc;
+    xc.h = __builtin_amdgcn_readlane(v.h, c);
+    xc.e = __builtin_amdgcn_readlane(v.e, c);
+    const bool xnar = __builtin_amdgcn_readlane((int)vnar, c) != 0;
     if (lane > c && lane < w) {
-      const uint32_t m = Ls[lane][c];
-      if (m == kNaR || xc == kNaR) vnar = true;
-      else if (!vnar) v = fms_win(v, decode(xc), decode(m));
+      const int2 m = Ls[lane][c];
+      if (m.y == kScNaR || xnar) vnar = true;
+      else if (!vnar) {
+        dec md;
+        md.s = m.x;
+        md.sc = m.y;
+        v = fms_win(v, md, dec_of_win(xc));
+      }
     }
   }
   if (lane < w) row[lane] = vnar ? kNaR : encode_win(v);
@@ -489,7 +523,6 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
 // every later row r gets x[r] - rnd(T(r,c) x[c]).  No barrier or LDS access
 // on the chain itself.
 constexpr int kTrsvBlock = 64;
-constexpr int32_t kScNaR = 1 << 20;              // scale field of a staged NaR coefficient
 
 __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,

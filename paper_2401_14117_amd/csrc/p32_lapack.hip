@@ -647,6 +647,10 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t count, unsigned l
   if (i < count) p[i] = v;
 }
 
+#ifndef P32_PANEL_MIN_ROWS
+#define P32_PANEL_MIN_ROWS 4      // fewest panel rows per workgroup
+#endif
+
 int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                  int32_t* info) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
@@ -684,7 +688,7 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
     const int64_t jb = nb < n - j ? nb : n - j;
     const int64_t rows = n - j;
     int64_t R = (rows + gmax - 1) / gmax;
-    if (R < 8) R = 8;
+    if (R < P32_PANEL_MIN_ROWS) R = P32_PANEL_MIN_ROWS;
     const int64_t G = (rows + R - 1) / R;
     const bool lds = R * jb <= kPanelLds;
     if (G > (lds ? per_cu_lds : per_cu_glb) * (int64_t)cus) {

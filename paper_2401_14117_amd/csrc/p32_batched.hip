@@ -429,11 +429,16 @@ struct Batch {
 
 // KIND 0: LU, 1: Cholesky.  FACTOR / SOLVE select the phases; with both, a
 // failed factorisation (info > 0) skips the solve.
-// (Everything is inlined into the kernel and the register budget is two
-// waves per SIMD: the tile routine alone needs about 124 VGPRs, and with the
-// kernel's own live state a tighter budget spills inside its inner loop.)
+// Everything is inlined into the kernel, with a register budget of four waves
+// per SIMD (128 VGPRs).  That spills 200-350 bytes per lane to scratch, but the
+// extra waves hide the latency of the unblocked steps' barriers and divisions:
+// on the 20,000-system batches 4 waves per SIMD run 23% faster than 2 (no
+// spills) and 6% faster than 3; 5 and 6 are no faster.
+#ifndef P32_BATCH_MIN_WAVES
+#define P32_BATCH_MIN_WAVES 4
+#endif
 template <int KIND, bool FACTOR, bool SOLVE>
-__global__ void __launch_bounds__(kBT, 2) vbatched_kernel(Batch bt) {
+__global__ void __launch_bounds__(kBT, P32_BATCH_MIN_WAVES) vbatched_kernel(Batch bt) {
   __shared__ Shared sh;
   for (int64_t idx = blockIdx.x; idx < bt.count; idx += gridDim.x) {
     const int64_t n = bt.n[idx];
@@ -485,14 +490,14 @@ int launch_kernel(hipStream_t s, const Batch& bt) {
 
 // Built-in sub-panel widths per size bucket, measured on MI355X (the
 // autotuner replaces them per device): a width >= n runs small systems
-// unblocked, 16 suits the LU of larger ones, 32 the larger Cholesky ones.
+// unblocked, 16 suits the LU of orders 48-95 and 32 the larger systems.
 Tuning default_tuning(int kind) {
   Tuning t{};
-  t.buckets = 5;
-  const int32_t max_n[5] = {31, 63, 127, 255, 0x7FFFFFFF};
-  const int32_t lu[5] = {32, 64, 16, 16, 16};
-  const int32_t chol[5] = {32, 64, 16, 32, 32};
-  for (int b = 0; b < 5; ++b) {
+  t.buckets = 6;
+  const int32_t max_n[6] = {23, 47, 95, 191, 383, 0x7FFFFFFF};
+  const int32_t lu[6] = {48, 48, 16, 32, 32, 32};
+  const int32_t chol[6] = {48, 48, 32, 32, 32, 32};
+  for (int b = 0; b < 6; ++b) {
     t.max_n[b] = max_n[b];
     t.sub[b] = kind == 0 ? lu[b] : chol[b];
   }

@@ -26,12 +26,59 @@
 #include <hip/hip_runtime.h>
 
 #include "p32_device.hpp"
+#include "p32_gemm_tile.hpp"
 #include "p32_launch.hpp"
 
 namespace p32 {
 
 constexpr int kMaxNB = 256;
 constexpr uint32_t kMinusOne = 0xC0000000u;
+
+// ---- one fused update of a running value -----------------------------------
+// acc <- rnd(acc - rnd(m * x)) for one lane's running value acc (biased window
+// form, as in the Rgemm tile), with the Rgemm's unchecked k-step arithmetic
+// (staged operands, rounding parameters from the LDS table) when m, x and acc
+// lie in its proven range: m and x nonzero with scales in [-53, 49], acc with
+// scale in [-106, 100], so that the one step stays inside the table and the
+// fast range.  Otherwise, and when the sum cancels or aligns past the fast
+// path's reach, the lane takes the exact routines.  A zero m leaves acc as it
+// is (acc - 0 is acc exactly).  dm: m decoded (not NaR); bx: x staged as an
+// op(B) operand, nonzero and not NaR (a zero x leaves every running value
+// unchanged and is skipped by the caller); x_ok: x's scale in the proven
+// range.  Out of range, the table is indexed with stand-in operands (1 and
+// -1), so every table access stays inside the table.
+__device__ __forceinline__ bool scale_proven(int sc) { return (unsigned)(sc + 53) <= 102u; }
+
+// the exact path of chain_update, out of line so that unrolled chains stay
+// small in the instruction cache
+static __device__ __noinline__ win chain_update_slow(win acc, dec dm, dec dx) {
+  return bias(fms_win(unbias(acc), dm, dx));
+}
+
+__device__ __forceinline__ win chain_update(win acc, dec dm, int2 bx, bool x_ok, const lut_t* lut) {
+  const bool m_ok = dm.s != 0 && scale_proven(dm.sc);
+  const int2 a = m_ok ? stage_a(dm, true) : make_int2(-(1 << 30), 16 * 128);
+  const int2 b = x_ok ? bx : make_int2(1 << 29, 0);
+  uint32_t badbits = 0;
+  const win pr = mul_unchecked(a, b, lut);
+  win nacc = add_unchecked(acc, pr, lut, badbits);
+  const bool acc_ok = (unsigned)(acc.e - EB + 106) <= 206u;   // a zero acc fails this
+  if ((dm.s != 0) & (!(m_ok & x_ok & acc_ok) | (badbits > 63u))) {
+    dec dx;
+    dx.s = bx.x >> 2;
+    dx.sc = bx.y >> 4;
+    nacc = chain_update_slow(acc, dm, dx);
+  }
+  return dm.s != 0 ? nacc : acc;
+}
+
+// stand-in running value for lanes without a row (kept in the proven range)
+__device__ __forceinline__ win idle_acc() {
+  win w;
+  w.h = 1 << 27;
+  w.e = EB;
+  return w;
+}
 
 // ---- LU panel --------------------------------------------------------------
 
@@ -310,22 +357,24 @@ __global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, i
 // column q of A12, thread r owns row j + r of it and keeps it decoded (window
 // form, plus a NaR flag) across the column steps.  Per column c in ascending
 // order the owner of row c, final once its own last update is in, publishes
-// it through LDS as a pattern and decoded (double-buffered by parity); after
-// one barrier every row r > c gets x[r] - rnd(L11[r][c] x[c]).  Each thread
-// reads its own row of L11, contiguous in memory, kTrsmPrefetch coefficients
-// ahead.
+// it through LDS decoded, with its NaR flag (double-buffered by parity); after
+// one barrier every row r > c gets x[r] - rnd(L11[r][c] x[c]) (chain_update).
+// Each thread reads its own row of L11, contiguous in memory, kTrsmPrefetch
+// coefficients ahead.
 constexpr int kTrsmPrefetch = 8;
 
 __global__ void __launch_bounds__(256)
 trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb) {
-  __shared__ uint32_t xc_p[2];
+  __shared__ int xc_nar[2];
   __shared__ dec xc_d[2];
+  __shared__ lut_t lut[256];
   const int t = threadIdx.x;
+  lut[t] = make_lut_entry(t);
   const int64_t q = j + jb + blockIdx.x;
   const bool mine = t < jb;
   const uint32_t x0 = mine ? A[(j + t) * lda + q] : 0u;
   bool xnar = x0 == kNaR;
-  win x = win_of(xnar ? 0u : x0);
+  win acc = mine ? bias(win_of(xnar ? 0u : x0)) : idle_acc();   // biased window form
   const uint32_t* Lrow = A + (j + (mine ? t : 0)) * lda + j;
   uint32_t cur[kTrsmPrefetch], nxt[kTrsmPrefetch];
 #pragma unroll
@@ -342,15 +391,15 @@ trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int6
       const int c = c0 + i;
       if (c < jb) {
         if (t == c) {
-          const uint32_t pc = xnar ? kNaR : encode_win(x);
-          xc_p[par] = pc;
-          xc_d[par] = decode(pc);
+          xc_nar[par] = xnar;
+          xc_d[par] = dec_of_win(unbias(acc));
         }
         __syncthreads();
         if (t > c && mine) {
-          const uint32_t l = cur[i], xp = xc_p[par];
-          if (l == kNaR || xp == kNaR) xnar = true;
-          else if (!xnar) x = fms_win(x, decode(l), xc_d[par]);
+          const uint32_t l = cur[i];
+          const dec dx = xc_d[par];
+          if (l == kNaR || xc_nar[par]) xnar = true;
+          else if (!xnar && dx.s != 0) acc = chain_update(acc, decode(l), stage_b(dx), scale_proven(dx.sc), lut);
         }
         par ^= 1;
       }
@@ -358,7 +407,7 @@ trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int6
 #pragma unroll
     for (int i = 0; i < kTrsmPrefetch; ++i) cur[i] = nxt[i];
   }
-  if (mine) A[(j + t) * lda + q] = xnar ? kNaR : encode_win(x);
+  if (mine) A[(j + t) * lda + q] = xnar ? kNaR : encode_win(unbias(acc));
 }
 
 // ---- Cholesky --------------------------------------------------------------
@@ -437,9 +486,10 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
 // at A[j][j] (jb <= kCholTrsmMax): one wave per row, lane t holds column
 // j + t.  Column by column: x_c = A[r][c] / L[c][c] is final once the updates
 // from columns < c are in, then columns c' > c get A[r][c'] - rnd(x_c *
-// L[c'][c]).  The triangle is staged in LDS once per workgroup (four rows),
-// already decoded; lane c keeps L[c][c] with a binary64 reciprocal for its
-// quotient, and the new x_c reaches the other lanes through v_readlane.
+// L[c'][c]) (chain_update).  The triangle is staged in LDS once per
+// workgroup (four rows), already decoded; lane c keeps L[c][c] with a binary64
+// reciprocal for its quotient, and the new x_c reaches the other lanes through
+// v_readlane.
 constexpr int kCholTrsmMax = 64;
 constexpr int32_t kScNaR = 1 << 20;              // scale field of a staged NaR coefficient
 
@@ -447,15 +497,29 @@ __global__ void __launch_bounds__(256)
 trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t r_end, int64_t j,
                  int64_t jb, const int32_t* __restrict__ info) {
   __shared__ int2 Ls[kCholTrsmMax][kCholTrsmMax + 1];   // decoded, NaR as scale kScNaR
+  __shared__ lut_t lut[256];
   if (*info != 0) return;
+  lut[threadIdx.x] = make_lut_entry((int)threadIdx.x);
   const int lane = threadIdx.x & 63;
   const int w = (int)jb;
-  for (int idx = threadIdx.x; idx < w * w; idx += 256) {
-    const int cc = idx / w, c = idx - cc * w;
-    if (c <= cc) {
-      const uint32_t m = A[(j + cc) * lda + j + c];
-      const dec d = decode(m);
-      Ls[cc][c] = make_int2(d.s, m == kNaR ? kScNaR : d.sc);
+  {
+    // all of a thread's loads are issued before the first is decoded
+    constexpr int kPer = kCholTrsmMax * kCholTrsmMax / 256;
+    uint32_t mv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int idx = (int)threadIdx.x + i * 256;
+      const int cc = idx / kCholTrsmMax, c = idx % kCholTrsmMax;
+      mv[i] = cc < w && c <= cc ? A[(j + cc) * lda + j + c] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int idx = (int)threadIdx.x + i * 256;
+      const int cc = idx / kCholTrsmMax, c = idx % kCholTrsmMax;
+      if (cc < w && c <= cc) {
+        const dec d = decode(mv[i]);
+        Ls[cc][c] = make_int2(d.s, mv[i] == kNaR ? kScNaR : d.sc);
+      }
     }
   }
   __syncthreads();
@@ -475,31 +539,32 @@ trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t
     dg_bad = d2.y == kScNaR || d2.x == 0;
     if (!dg_bad) rcp = 1.0 / (double)(dg.s < 0 ? -(int64_t)dg.s : (int64_t)dg.s);
   }
-  // lane c's value, kept decoded (window form plus a NaR flag)
+  // lane c's value, kept decoded (biased window form plus a NaR flag)
   const uint32_t v0 = lane < w ? row[lane] : 0u;
   bool vnar = v0 == kNaR;
-  win v = win_of(vnar ? 0u : v0);
+  win acc = lane < w ? bias(win_of(vnar ? 0u : v0)) : idle_acc();
   for (int c = 0; c < w; ++c) {
     if (lane == c) {
       if (dg_bad) vnar = true;
-      else if (!vnar) v = div_win(dec_of_win(v), dg, rcp);
+      else if (!vnar) acc = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
     }
     win xc;
-    xc.h = __builtin_amdgcn_readlane(v.h, c);
-    xc.e = __builtin_amdgcn_readlane(v.e, c);
+    xc.h = __builtin_amdgcn_readlane(acc.h, c);
+    xc.e = __builtin_amdgcn_readlane(acc.e, c);
     const bool xnar = __builtin_amdgcn_readlane((int)vnar, c) != 0;
+    const dec dx = dec_of_win(unbias(xc));                 // x_c, wave-uniform
     if (lane > c && lane < w) {
       const int2 m = Ls[lane][c];
       if (m.y == kScNaR || xnar) vnar = true;
-      else if (!vnar) {
+      else if (!vnar && dx.s != 0) {                       // x_c = 0 changes nothing
         dec md;
         md.s = m.x;
         md.sc = m.y;
-        v = fms_win(v, md, dec_of_win(xc));
+        acc = chain_update(acc, md, stage_b(dx), scale_proven(dx.sc), lut);
       }
     }
   }
-  if (lane < w) row[lane] = vnar ? kNaR : encode_win(v);
+  if (lane < w) row[lane] = vnar ? kNaR : encode_win(unbias(acc));
 }
 
 // ---- triangular solves -----------------------------------------------------
@@ -520,7 +585,7 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
 // column c in solve order, the owner lane of row c (final once its own last
 // update is in) divides it by the diagonal (non-unit kinds); the quotient is
 // read by every lane with v_readlane (the column index is wave-uniform), and
-// every later row r gets x[r] - rnd(T(r,c) x[c]).  No barrier or LDS access
+// every later row r gets x[r] - rnd(T(r,c) x[c]) (chain_update).  No barrier
 // on the chain itself.
 constexpr int kTrsvBlock = 64;
 
@@ -528,19 +593,34 @@ __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
                  int64_t nrhs, int64_t s, int bs, int kind) {
   __shared__ int2 coef[kTrsvBlock][kTrsvBlock + 1];
+  __shared__ lut_t lut[256];
   const bool forward = kind == 0 || kind == 2;
   const bool unit = kind == 0;
   const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
-  // coef[r][u]: coefficient of the u-th column in solve order in row r, decoded
-  for (int idx = lane; idx < bs * bs; idx += kTrsvBlock) {
-    int r, u;
-    if (kind == 3) { u = idx / bs; r = idx - u * bs; }     // row c of M is contiguous in r
-    else { r = idx / bs; u = idx - r * bs; }
-    const int64_t c = forward ? s + u : s + bs - 1 - u;
-    const uint32_t m = tri_coef(M, lda, kind, s + r, c);
-    const dec d = decode(m);
-    coef[r][u] = make_int2(d.s, m == kNaR ? kScNaR : d.sc);
+  // coef[r][u]: coefficient of the u-th column in solve order in row r,
+  // decoded; only the entries strictly below the diagonal in solve order are
+  // loaded.  The lane index is u (kinds 0..2: a row of M is contiguous) or r
+  // (kind 3: a column of M is), and all of a lane's loads are issued before
+  // the first is decoded, so the staging waits on memory once, not per row.
+  {
+    const bool trans = kind == 3;
+    uint32_t mv[kTrsvBlock];
+#pragma unroll
+    for (int a = 0; a < kTrsvBlock; ++a) {
+      const int r = trans ? lane : a, u = trans ? a : lane;
+      const bool need = a < bs && lane < bs && (forward ? r > u : r + u < bs - 1);
+      const int64_t c = forward ? s + u : s + bs - 1 - u;
+      mv[a] = need ? tri_coef(M, lda, kind, s + r, c) : 0u;
+    }
+#pragma unroll
+    for (int a = 0; a < kTrsvBlock; ++a) {
+      const int r = trans ? lane : a, u = trans ? a : lane;
+      if (a < bs && lane < bs) {
+        const dec d = decode(mv[a]);
+        coef[r][u] = make_int2(d.s, mv[a] == kNaR ? kScNaR : d.sc);
+      }
+    }
   }
   // this lane's diagonal entry (the divisor when it owns the column)
   dec dg;
@@ -556,52 +636,95 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
   }
   const uint32_t x0 = lane < bs ? B[(s + lane) * ldb + q] : 0u;
   bool xnar = x0 == kNaR;
-  win x = win_of(xnar ? 0u : x0);
+  win acc = lane < bs ? bias(win_of(xnar ? 0u : x0)) : idle_acc();   // biased window form
+  for (int i = lane; i < 256; i += kTrsvBlock) lut[i] = make_lut_entry(i);
   __syncthreads();
   for (int u = 0; u < bs; ++u) {
     const int cl = forward ? u : bs - 1 - u;                // local column (wave-uniform)
     if (!unit && lane == cl) {
       if (dg_bad) xnar = true;
-      else if (!xnar) x = div_win(dec_of_win(x), dg, rcp);
+      else if (!xnar) acc = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
     }
     win pc;
-    pc.h = __builtin_amdgcn_readlane(x.h, cl);
-    pc.e = __builtin_amdgcn_readlane(x.e, cl);
+    pc.h = __builtin_amdgcn_readlane(acc.h, cl);
+    pc.e = __builtin_amdgcn_readlane(acc.e, cl);
     const bool pnar = __builtin_amdgcn_readlane((int)xnar, cl) != 0;
+    const dec dx = dec_of_win(unbias(pc));                 // x[c], wave-uniform
     const bool below = forward ? lane > cl : lane < cl;
     if (lane < bs && below) {
       const int2 m = coef[lane][u];
       if (m.y == kScNaR || pnar) xnar = true;
-      else if (!xnar) {
+      else if (!xnar && dx.s != 0) {                       // x[c] = 0 changes nothing
         dec md;
         md.s = m.x;
         md.sc = m.y;
-        x = fms_win(x, md, dec_of_win(pc));
+        acc = chain_update(acc, md, stage_b(dx), scale_proven(dx.sc), lut);
       }
     }
   }
-  if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(x);
+  if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(unbias(acc));
 }
 
-// rows outside the diagonal block [s, s+bs) get that block's columns, in
-// ascending order (forward) or descending order (backward)
-__global__ void trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B,
-                                   int64_t ldb, int64_t nrhs, int64_t s, int64_t bs, int64_t r0,
-                                   int64_t r1, int kind) {
+// Rows outside the diagonal block [s, s+bs) get that block's columns, in
+// ascending order (forward) or descending order (backward).  One wave per 64
+// rows and one right-hand side q: lane u holds the block's u-th solved entry
+// (in solve order) staged as an op(B) operand, and at step u every lane reads
+// it with v_readlane.  Each lane's own coefficients are loaded kTrsvChunk
+// steps ahead of its chain of updates, so the chain does not wait on memory
+// step by step.  A NaR among the block's entries reaches every row.
+constexpr int kTrsvChunk = 16;
+
+__global__ void __launch_bounds__(kTrsvBlock)
+trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
+                   int64_t nrhs, int64_t s, int bs, int64_t r0, int64_t r1, int kind) {
+  __shared__ lut_t lut[256];
+  for (int i = threadIdx.x; i < 256; i += kTrsvBlock) lut[i] = make_lut_entry(i);
+  __syncthreads();
   const bool forward = kind == 0 || kind == 2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (r1 - r0) * nrhs) return;
-  const int64_t r = r0 + idx / nrhs, q = idx % nrhs;
-  const uint32_t x0 = B[r * ldb + q];
-  bool xnar = x0 == kNaR;                         // the running value, kept decoded
-  win x = win_of(xnar ? 0u : x0);
-  for (int64_t step = 0; step < bs; ++step) {
-    const int64_t c = forward ? s + step : s + bs - 1 - step;
-    const uint32_t m = tri_coef(M, lda, kind, r, c), b = B[c * ldb + q];
-    if (m == kNaR || b == kNaR) xnar = true;
-    else if (!xnar) x = fms_win(x, decode(m), decode(b));
+  const int lane = threadIdx.x;
+  const int64_t r = r0 + (int64_t)blockIdx.x * kTrsvBlock + lane;
+  const bool mine = r < r1;
+  const int64_t rr = mine ? r : r0;               // a row in range, for the coefficient loads
+  const int64_t cl = forward ? s + lane : s + bs - 1 - lane;
+  for (int64_t q = blockIdx.y; q < nrhs; q += gridDim.y) {
+    const uint32_t bl = lane < bs ? B[cl * ldb + q] : 0u;
+    const int2 xs = stage_b(decode(bl));          // NaR stages as zero; flagged below
+    const bool bnar = __ballot(bl == kNaR) != 0ull;
+    const uint32_t x0 = mine ? B[r * ldb + q] : 0u;
+    bool xnar = x0 == kNaR || bnar;
+    win acc = mine ? bias(win_of(x0 == kNaR ? 0u : x0)) : idle_acc();
+    // Coefficient loads are unconditional (steps past the block re-read its
+    // last column and are not used), so the compiler sees a straight run of
+    // loads and waits only for the chunk it is about to use.
+    uint32_t cur[kTrsvChunk], nxt[kTrsvChunk];
+#pragma unroll
+    for (int i = 0; i < kTrsvChunk; ++i) {
+      const int step = min(i, bs - 1);
+      cur[i] = tri_coef(M, lda, kind, rr, forward ? s + step : s + bs - 1 - step);
+    }
+    for (int c0 = 0; c0 < bs; c0 += kTrsvChunk) {
+#pragma unroll
+      for (int i = 0; i < kTrsvChunk; ++i) {
+        const int step = min(c0 + kTrsvChunk + i, bs - 1);
+        nxt[i] = tri_coef(M, lda, kind, rr, forward ? s + step : s + bs - 1 - step);
+      }
+#pragma unroll
+      for (int i = 0; i < kTrsvChunk; ++i) {
+        const int step = c0 + i;
+        if (step < bs) {
+          const uint32_t m = cur[i];
+          if (m == kNaR) xnar = true;
+          int2 bx;
+          bx.x = __builtin_amdgcn_readlane(xs.x, step);
+          bx.y = __builtin_amdgcn_readlane(xs.y, step);
+          if (bx.x != 0 && m != kNaR) acc = chain_update(acc, decode(m), bx, scale_proven(bx.y >> 4), lut);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kTrsvChunk; ++i) cur[i] = nxt[i];
+    }
+    if (mine) B[r * ldb + q] = xnar ? kNaR : encode_win(unbias(acc));
   }
-  B[r * ldb + q] = xnar ? kNaR : encode_win(x);
 }
 
 // row interchanges of getrs, in order, one thread per right-hand side
@@ -632,10 +755,11 @@ static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32
     hipLaunchKernelGGL(trsv_diag_kernel, dim3((unsigned)nrhs), dim3(kTrsvBlock), 0, s, M, lda, B, ldb,
                        nrhs, s0, (int)bs, kind);
     const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? n : s0;
-    const int64_t cnt = (r1 - r0) * nrhs;
-    if (cnt > 0)
-      hipLaunchKernelGGL(trsv_update_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, M,
-                         lda, B, ldb, nrhs, s0, bs, r0, r1, kind);
+    if (r1 > r0) {
+      const unsigned gy = (unsigned)(nrhs < 65535 ? nrhs : 65535);
+      hipLaunchKernelGGL(trsv_update_kernel, dim3((unsigned)((r1 - r0 + kTrsvBlock - 1) / kTrsvBlock), gy),
+                         dim3(kTrsvBlock), 0, s, M, lda, B, ldb, nrhs, s0, (int)bs, r0, r1, kind);
+    }
   }
   return launch_status();
 }

@@ -135,3 +135,47 @@ def test_n768_parity(P, kind):
         gL, ginfo = _gpu_potrf(P, A, 256)
         assert ginfo == info == 0
         assert np.array_equal(gL, L), _diff(gL, L)
+
+
+
+def _solve_case(n, nrhs, where):
+    """A factor and right-hand sides holding one kind of special value:
+    'u': NaR in U near the top (only the rows above it turn NaR in getrs),
+    'l': NaR in L, 'b': NaR in B, 'z': zero diagonal entries near the top
+    and the bottom (NaR quotients)."""
+    rng = np.random.default_rng(7 * n + nrhs)
+    M = p32(rng.uniform(-1, 1, (n, n)) * 2.0 ** rng.integers(-4, 5, (n, n)))
+    B = p32(rng.uniform(-1, 1, (n, nrhs)))
+    if where == "u" and n > 3:
+        M[2, max(3, n - 40)] = NAR
+    elif where == "l" and n > 1:
+        M[n - 1, n // 2] = NAR
+    elif where == "b":
+        B[n // 2, nrhs - 1] = NAR
+    elif where == "z":
+        M[min(5, n - 1), min(5, n - 1)] = 0
+        M[n - 1, n - 1] = 0
+    ipiv = np.arange(n, dtype=np.int32)
+    for c in range(0, n, 7):
+        ipiv[c] = rng.integers(c, n)
+    return M, B, ipiv
+
+
+@pytest.mark.parametrize("where", ["u", "l", "b", "z"])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 1), (65, 70), (150, 5), (200, 2)])
+def test_solves_with_nar_and_zero_diagonal(P, n, nrhs, where):
+    """getrs and potrs on a given factor with NaR entries or zero diagonal
+    entries, over one or more 64-row solve blocks with a ragged tail and
+    many right-hand sides; bit for bit against the oracle."""
+    import torch
+    M, B, ipiv = _solve_case(n, nrhs, where)
+    X = O.getrs(M, ipiv, B)
+    if where == "u" and n > 64:
+        assert 0 < np.count_nonzero(X == NAR) < X.size    # NaR reaches only the rows above
+    Bd = to_dev(B)
+    P.getrs(to_dev(M), torch.from_numpy(ipiv).cuda(), Bd)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+    X = O.potrs(M, B)
+    Bd = to_dev(B)
+    P.potrs(to_dev(M), Bd)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)

@@ -422,9 +422,12 @@ __device__ __forceinline__ dec dec_of_win(win w) {
 
 // rnd(a / b) in window form for decoded a, b (b nonzero, neither NaR), with
 // rcp_b = 1.0 / |b.s| computed beforehand (a divisor reused along a chain
-// costs one binary64 multiply per quotient).  The estimate num * rcp_b is
-// within one unit of the 37-bit integer quotient, which is then fixed up
-// exactly in integers; the remainder is the sticky bit.
+// costs one binary64 multiply per quotient).  Everything stays in binary64:
+// floor(num * rcp_b) is within one unit of the 37-bit integer quotient
+// q = floor(num / |b.s|), num = |a.s| 2^36; the remainder num - q |b.s| is
+// exact in one fused multiply-add (it is an integer below 2^30), which fixes
+// q up and gives the sticky bit; q, an integer below 2^37, is then read from
+// the bits of its binary64 representation.
 __device__ inline win div_win(dec a, dec b, double rcp_b) {
   win w;
   if (a.s == 0) {
@@ -433,22 +436,60 @@ __device__ inline win div_win(dec a, dec b, double rcp_b) {
     return w;
   }
   const bool neg = (a.s < 0) != (b.s < 0);
-  const uint64_t ma = (uint64_t)(a.s < 0 ? -(int64_t)a.s : a.s);
-  const uint64_t mb = (uint64_t)(b.s < 0 ? -(int64_t)b.s : b.s);
-  const uint64_t num = ma << 36;                 // 28 significant bits: exact in binary64
-  uint64_t q = (uint64_t)((double)num * rcp_b);
-  int64_t r = (int64_t)(num - q * mb);
-  if (r < 0) { q -= 1; r += (int64_t)mb; }
-  else if (r >= (int64_t)mb) { q += 1; r -= (int64_t)mb; }
-  const int L = 63 - __clzll(q);                 // 35 or 36: q in [2^35, 2^37)
+  const double ma = (double)(a.s < 0 ? -a.s : a.s);
+  const double mb = (double)(b.s < 0 ? -b.s : b.s);
+  const double num = ma * 68719476736.0;          // |a.s| 2^36, exact
+  double q = floor(num * rcp_b);
+  double r = fma(-q, mb, num);                    // exact, |r| < 2 |b.s|
+  const double adj = r < 0.0 ? -1.0 : (r >= mb ? 1.0 : 0.0);
+  q += adj;
+  r = fma(-adj, mb, r);
+  // q in [2^35, 2^37): significand bits [51:0] of q hold q below its leading bit
+  const uint64_t bits = (uint64_t)__double_as_longlong(q);
+  const uint32_t hi = (uint32_t)(bits >> 32), lo = (uint32_t)bits;
+  const int L = (int)(hi >> 20) - 1023;           // 35 or 36
   const int sc = a.sc - b.sc - 36 + L;
   if (scale_ok(sc)) {
-    const uint64_t qn = q << (60 - L);           // leading bit at 60
-    const uint32_t hi = (uint32_t)(qn >> 32), lo = (uint32_t)qn;
-    const int32_t h2 = (int32_t)(2u * hi + (uint32_t)((lo != 0u) | (r != 0)));
-    return round_h2(neg ? -h2 : h2, sc);         // round to nearest even is odd-symmetric
+    // the top 30 bits of the significand (leading bit at 29), the rest of
+    // it and the remainder folded into bit 0
+    const uint32_t top = ((hi & 0xFFFFFu) | 0x100000u) << 9 | (lo >> 23);
+    const int32_t h2 = (int32_t)((top & ~1u) | (uint32_t)(((lo & 0xFFFFFFu) != 0u) | (r != 0.0)));
+    return round_h2(neg ? -h2 : h2, sc);          // round to nearest even is odd-symmetric
   }
-  return win_of(round_general64(neg, q, a.sc - b.sc - 36, r != 0));
+  const uint64_t qi = ((((uint64_t)(hi & 0xFFFFFu) | 0x100000u) << 32) | lo) >> (52 - L);
+  return win_of(round_general64(neg, qi, a.sc - b.sc - 36, r != 0.0));
+}
+
+// rnd(sqrt(a)) in window form for a decoded a > 0.  With a = m 2^x, x even,
+// v = m 2^34 (at most 29 significant bits, exact in binary64) and r =
+// floor(sqrt(v)): the binary64 square root is within one unit of r, and
+// r^2 - v, an integer below 2^34 in magnitude, is exact in one fused
+// multiply-add, which fixes r up and gives the sticky bit.  sqrt(a) =
+// (r + f) 2^(x/2 - 17) with 0 <= f < 1; its scale is inside the fast range.
+__device__ inline win sqrt_win(dec a) {
+  int x = a.sc - 27;                              // a = a.s 2^x
+  double m = (double)a.s;
+  if (x & 1) {
+    m *= 2.0;
+    x -= 1;
+  }
+  const double v = m * 17179869184.0;             // m 2^34, exact
+  double r = floor(sqrt(v));
+  double d = fma(r, r, -v);                       // r^2 - v, exact
+  if (d > 0.0) {
+    d -= 2.0 * r - 1.0;
+    r -= 1.0;
+  } else if (d + 2.0 * r + 1.0 <= 0.0) {
+    d += 2.0 * r + 1.0;
+    r += 1.0;
+  }
+  const uint32_t ri = (uint32_t)r;                // in [2^30, 2^32)
+  const int L = 31 - __clz(ri);                   // 30 or 31
+  const int sh = L - 28;                          // 2 or 3
+  const uint32_t kept = ri >> sh;                 // leading bit at 28
+  const uint32_t lost = ri & ((1u << sh) - 1u);
+  const int32_t h2 = (int32_t)(2u * kept + (uint32_t)((lost != 0u) | (d != 0.0)));
+  return round_h2(h2, x / 2 - 17 + L);
 }
 
 // A divisor prepared once for many quotients: decoded, with its binary64
@@ -513,7 +554,11 @@ __device__ inline uint32_t p_div(uint32_t a, uint32_t b) {
   return div_general(decode(a), decode(b), a == kNaR, b == kNaR);
 }
 
-__device__ inline uint32_t p_sqrt(uint32_t a) { return sqrt_general(decode(a), a == kNaR); }
+__device__ inline uint32_t p_sqrt(uint32_t a) {
+  if (a == kNaR || (int32_t)a < 0) return kNaR;
+  if (a == 0u) return 0u;
+  return encode_win(sqrt_win(decode(a)));
+}
 
 // key of |x| for pivot search: posit order is signed-integer order of the
 // patterns and |NaR| = NaR is the smallest; ties prefer the smaller row

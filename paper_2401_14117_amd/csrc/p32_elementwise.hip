@@ -1,8 +1,8 @@
 // p32_elementwise.hip -- conversions and elementwise Posit(32,2) arithmetic
 // (the paper's Add/Mul/Div/Sqrt kernels, Section 4.2): add, multiply and
-// divide take the window-form fast path with the exact routines as fallback
-// (the quotient from a binary64 estimate fixed up exactly in integers),
-// square root the exact routine.  Grid-stride loops; every element
+// divide take the window-form fast path with the exact routines as fallback;
+// the quotient and the square root come from binary64 estimates fixed up
+// exactly with one fused multiply-add each.  Grid-stride loops; every element
 // independent.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -79,7 +79,7 @@ __global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict
         break;
       }
       default:
-        r = sqrt_general(decode(x), xn);
+        r = p_sqrt(x);
         break;
     }
     out[i] = r;

@@ -80,6 +80,15 @@ __device__ __forceinline__ win idle_acc() {
   return w;
 }
 
+// rnd(c - rnd(l x)) on patterns by chain_update: x given as its pattern xp
+// (for the NaR test) and staged as an op(B) operand bx
+__device__ __forceinline__ uint32_t fms_staged(uint32_t c, uint32_t l, uint32_t xp, int2 bx,
+                                               const lut_t* lut) {
+  if (c == kNaR || l == kNaR || xp == kNaR) return kNaR;
+  if (bx.x == 0) return c;                        // c - rnd(l 0) = c
+  return encode_win(unbias(chain_update(bias(win_of(c)), decode(l), bx, scale_proven(bx.y >> 4), lut)));
+}
+
 // ---- LU panel --------------------------------------------------------------
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
@@ -165,8 +174,9 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
                 uint32_t* __restrict__ rowc, int32_t* __restrict__ ipiv, int32_t* __restrict__ info) {
   __shared__ uint32_t tile[LDS ? kPanelLds : 1];
   __shared__ uint32_t urow[kMaxNB];
-  __shared__ dec udec[kMaxNB];
+  __shared__ int2 ustg[kMaxNB];                   // urow staged as op(B) operands
   __shared__ unsigned long long red[2][kPanelThreads / 64];
+  __shared__ lut_t lut[256];
 
   const int t = threadIdx.x;
   const unsigned G = gridDim.x;
@@ -177,6 +187,7 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
   const int64_t ts = LDS ? jb : lda;              // row stride of T
   int rpar = 0;                                   // parity of the reduction buffer
 
+  if (t < 256) lut[t] = make_lut_entry(t);
   if (LDS) {
     for (int idx = t; idx < nr * jb; idx += kPanelThreads) {
       const int rr = idx / jb, q = idx - rr * jb;
@@ -263,8 +274,7 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
       const int dr = idx / wq;
       const int rr = ra + dr, q = qa + (idx - dr * wq);
       if (rr == skip1 || rr == skip2) continue;
-      const uint32_t l = T[rr * ts + cl];
-      T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+      T[rr * ts + q] = fms_staged(T[rr * ts + q], T[rr * ts + cl], urow[q], ustg[q], lut);
     }
   };
 
@@ -286,7 +296,7 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     for (int q = t; q < jb; q += kPanelThreads) {
       const uint32_t u = read_u32(crow + ((size_t)par * G + wp) * jb + q);
       urow[q] = u;
-      udec[q] = decode(u);
+      ustg[q] = stage_b(decode(u));
       if (own_c) T[(c - r0) * ts + q] = u;
       if (own_p) T[(p - r0) * ts + q] = read_u32(rowc + (size_t)par * jb + q);
     }
@@ -319,8 +329,7 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
         const int k = idx / wq;
         const int rr = (k == 0 && rw >= 0) ? rw : rc1;
         const int q = cl + 2 + (idx - k * wq);
-        const uint32_t l = T[rr * ts + cl];
-        T[rr * ts + q] = p_fms_pre(T[rr * ts + q], l, decode(l), urow[q], udec[q]);
+        T[rr * ts + q] = fms_staged(T[rr * ts + q], T[rr * ts + cl], urow[q], ustg[q], lut);
       }
     }
     __syncthreads();
@@ -427,9 +436,11 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
              const uint32_t* __restrict__ saved) {
   __shared__ uint32_t D[kTri];
   __shared__ uint32_t col[kMaxNB];
-  __shared__ dec cold[kMaxNB];                    // col, decoded
+  __shared__ int2 cstg[kMaxNB];                   // col staged as op(B) operands
+  __shared__ lut_t lut[256];
   __shared__ int stop;
   const int t = threadIdx.x;
+  if (t < 256) lut[t] = make_lut_entry(t);
   uint32_t* G = A + j * lda + j;
   if (saved == nullptr) {
     if (*info != 0) return;
@@ -463,7 +474,7 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
       const uint32_t x = a == kNaR ? kNaR : encode_win(div_win(decode(a), dd, rcp));
       D[tri_off(r) + c] = x;
       col[r] = x;
-      cold[r] = decode(x);
+      cstg[r] = stage_b(decode(x));
     }
     __syncthreads();
     // trailing triangle: local row a = i-c-1, local column b = q-c-1 <= a
@@ -474,7 +485,7 @@ potf2_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t j, int jb, int32_t* 
       if (tri_off(a + 1) <= idx) ++a;
       if (tri_off(a) > idx) --a;
       const int i = c + 1 + a, q = c + 1 + (idx - tri_off(a));
-      D[tri_off(i) + q] = p_fms_pre(D[tri_off(i) + q], col[i], cold[i], col[q], cold[q]);
+      D[tri_off(i) + q] = fms_staged(D[tri_off(i) + q], col[i], col[q], cstg[q], lut);
     }
     __syncthreads();
   }

@@ -121,17 +121,29 @@ constexpr unsigned kPollLimit = 1u << 20;
 // Everything one workgroup publishes for another (slots and row copies) is
 // written and read with agent-scope relaxed atomics, which on gfx950 go to
 // the device-coherent level of the memory hierarchy instead of a compute
-// unit's or an XCD's private caches.  A workgroup writes its row copies,
-// waits until its stores are acknowledged (s_waitcnt), joins a workgroup
-// barrier, and only then writes its slot; a reader issues its copy loads
-// only after it has seen every slot with the current tag.  Agent-scope
-// fences would give the same ordering but write back and invalidate the
-// whole L2 on every column step, which costs ten times more.
-__device__ __forceinline__ void publish_u32(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// unit's or an XCD's private caches.  No ordering between the stores is
+// needed: each word of a row copy carries the column it belongs to in its
+// high half, so a reader that has seen the slots polls the words it needs
+// until they carry the current column.  (Agent-scope fences would order the
+// stores but write back and invalidate the whole L2 on every column step,
+// ten times the cost; a store-completion wait plus a workgroup barrier
+// before the slot store costs one more memory round trip per column.)
+__device__ __forceinline__ void publish_tagged(unsigned long long* p, uint32_t c, uint32_t v) {
+  __hip_atomic_store(p, ((unsigned long long)c << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t read_u32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// the value of a tagged word once it carries column c; late is set when it
+// does not within kPollLimit rounds
+__device__ __forceinline__ uint32_t await_tagged(const unsigned long long* p, uint32_t c, int& late) {
+  unsigned long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (unsigned rounds = 0; (uint32_t)(v >> 32) != c;) {
+    if (++rounds > kPollLimit) {
+      late = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return (uint32_t)v;
 }
 
 __device__ __forceinline__ unsigned long long pivot_slot(uint32_t x, int64_t row, int64_t c) {
@@ -147,7 +159,7 @@ __device__ __forceinline__ int64_t slot_row(unsigned long long v) {
 // workgroups resident).  Workgroup w owns the R consecutive rows starting at
 // j + w R (in LDS when they fit, else in place in A).  Per column c:
 //   1. every workgroup has published its best pivot candidate for column c (a
-//      copy of the whole panel row, then its slot), and the owner of row c a
+//      copy of the whole panel row and its slot), and the owner of row c a
 //      copy of row c;
 //   2. every workgroup waits until all slots carry the tag of column c (this
 //      is the only grid-wide synchronisation) and takes the largest;
@@ -165,13 +177,18 @@ __device__ __forceinline__ int64_t slot_row(unsigned long long v) {
 // rows are only read from the published copies; copies and slots are
 // double-buffered by the parity of c (a workgroup can be at most one column
 // ahead of any other).  A wait that exceeds kPollLimit rounds gives up: info
-// is set to -1 and the workgroup exits, so no wave can wait forever.
-// Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb].
+// is set to -1 and the workgroup exits, so no wave can wait forever.  The
+// scaling, the look-ahead update of column c+1 and the candidate search give
+// row rr of the workgroup to the same thread, so they need no barrier
+// between them.
+// Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb], the row copies as
+// tagged words, every tag initially 0xFFFFFFFF (no column).
 template <bool LDS>
 __global__ void __launch_bounds__(kPanelThreads)
 lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int jb, int R,
-                unsigned long long* __restrict__ slot, uint32_t* __restrict__ crow,
-                uint32_t* __restrict__ rowc, int32_t* __restrict__ ipiv, int32_t* __restrict__ info) {
+                unsigned long long* __restrict__ slot, unsigned long long* __restrict__ crow,
+                unsigned long long* __restrict__ rowc, int32_t* __restrict__ ipiv,
+                int32_t* __restrict__ info) {
   __shared__ uint32_t tile[LDS ? kPanelLds : 1];
   __shared__ uint32_t urow[kMaxNB];
   __shared__ int2 ustg[kMaxNB];                   // urow staged as op(B) operands
@@ -212,32 +229,31 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     return b;
   };
 
-  // this workgroup's candidate for column c (rows >= c, column c up to date)
+  // this workgroup's candidate for column c (rows >= c, column c up to date;
+  // row rs + t + i kPanelThreads goes to thread t, as in the scaling and the
+  // look-ahead update)
   auto candidate = [&](int64_t c) {
     const int cl = (int)(c - j);
     unsigned long long best = 0ull;
-    for (int rr = t; rr < nr; rr += kPanelThreads)
-      if (r0 + rr >= c) {
-        const unsigned long long v = pivot_slot(T[rr * ts + cl], r0 + rr, c);
-        best = v > best ? v : best;
-      }
+    for (int rr = (int)max((int64_t)0, c - r0) + t; rr < nr; rr += kPanelThreads) {
+      const unsigned long long v = pivot_slot(T[rr * ts + cl], r0 + rr, c);
+      best = v > best ? v : best;
+    }
     return block_max(best);
   };
 
-  // step 1 for column c: copies of the candidate row and of row c (both up
-  // to date in every column), then the slot
+  // step 1 for column c: tagged copies of the candidate row and of row c
+  // (both up to date in every column), and the slot
   auto publish = [&](int64_t c, unsigned long long best) {
     const int par = (int)(c & 1);
     if ((best >> 8) != 0ull) {
       const int rr = (int)(slot_row(best) - r0);
-      uint32_t* dst = crow + ((size_t)par * G + w) * jb;
-      for (int q = t; q < jb; q += kPanelThreads) publish_u32(dst + q, T[rr * ts + q]);
+      unsigned long long* dst = crow + ((size_t)par * G + w) * jb;
+      for (int q = t; q < jb; q += kPanelThreads) publish_tagged(dst + q, (uint32_t)c, T[rr * ts + q]);
     }
     if (c >= r0 && c < r0 + nr)
       for (int q = t; q < jb; q += kPanelThreads)
-        publish_u32(rowc + (size_t)par * jb + q, T[(c - r0) * ts + q]);
-    __builtin_amdgcn_s_waitcnt(0);                // this wave's copies are acknowledged
-    __syncthreads();
+        publish_tagged(rowc + (size_t)par * jb + q, (uint32_t)c, T[(c - r0) * ts + q]);
     if (t == 0) {
       const unsigned long long v = (best >> 8) != 0ull ? best : (unsigned long long)(c & 0xFF);
       __hip_atomic_store(&slot[(size_t)par * G + w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -293,14 +309,18 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     const bool own_c = c >= r0 && c < r0 + nr;
     const bool own_p = p != c && p >= r0 && p < r0 + nr;
     // the pivot row (published copy of row p) becomes row c; row c's copy goes to row p
+    int late = 0;
     for (int q = t; q < jb; q += kPanelThreads) {
-      const uint32_t u = read_u32(crow + ((size_t)par * G + wp) * jb + q);
+      const uint32_t u = await_tagged(crow + ((size_t)par * G + wp) * jb + q, (uint32_t)c, late);
       urow[q] = u;
       ustg[q] = stage_b(decode(u));
       if (own_c) T[(c - r0) * ts + q] = u;
-      if (own_p) T[(p - r0) * ts + q] = read_u32(rowc + (size_t)par * jb + q);
+      if (own_p) T[(p - r0) * ts + q] = await_tagged(rowc + (size_t)par * jb + q, (uint32_t)c, late);
     }
-    __syncthreads();
+    if (__syncthreads_or(late)) {
+      if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
     const uint32_t piv = urow[cl];
     if (w == 0 && t == 0) {
       ipiv[c] = (int32_t)p;
@@ -312,12 +332,14 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
       const divisor pd = make_divisor(piv);
       for (int rr = rs + t; rr < nr; rr += kPanelThreads) T[rr * ts + cl] = p_div_by(T[rr * ts + cl], pd);
     }
-    __syncthreads();
-    if (cl + 1 == jb) break;
+    if (cl + 1 == jb) {
+      __syncthreads();                            // before the rows are written back
+      break;
+    }
     const int64_t c1 = c + 1;
-    // look-ahead: column c+1 of every row below c, then the candidate for it
+    // look-ahead: column c+1 of every row below c (row rs + idx to thread
+    // idx, as in the scaling), then the candidate for it
     update(cl, rs, nr, cl + 1, cl + 2, -1, -1);
-    __syncthreads();
     const unsigned long long nbest = candidate(c1);
     // complete the rows about to be published: the candidate and row c+1
     const int rw = (nbest >> 8) != 0ull ? (int)(slot_row(nbest) - r0) : -1;
@@ -807,17 +829,19 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
   if (gmax > kPanelThreads) gmax = kPanelThreads;
 
   const size_t slot_bytes = (size_t)2 * gmax * sizeof(unsigned long long);
-  const size_t row_bytes = (size_t)2 * gmax * kMaxNB * sizeof(uint32_t);
-  const size_t rowc_bytes = (size_t)2 * kMaxNB * sizeof(uint32_t);
+  const size_t row_bytes = (size_t)2 * gmax * kMaxNB * sizeof(unsigned long long);
+  const size_t rowc_bytes = (size_t)2 * kMaxNB * sizeof(unsigned long long);
   char* ws = nullptr;
   e = hipMallocAsync((void**)&ws, slot_bytes + row_bytes + rowc_bytes, s);
   if (e != hipSuccess) return -1000 - (int)e;
   unsigned long long* slot = reinterpret_cast<unsigned long long*>(ws);
-  uint32_t* crow = reinterpret_cast<uint32_t*>(ws + slot_bytes);
-  uint32_t* rowc = reinterpret_cast<uint32_t*>(ws + slot_bytes + row_bytes);
-  // tag 0xFF matches neither column 0 nor column 1
-  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((2 * gmax + 255) / 256)), dim3(256), 0, s, slot,
-                     (int64_t)(2 * gmax), ~0ull);
+  unsigned long long* crow = reinterpret_cast<unsigned long long*>(ws + slot_bytes);
+  unsigned long long* rowc = reinterpret_cast<unsigned long long*>(ws + slot_bytes + row_bytes);
+  // all ones: slot tag 0xFF matches neither column 0 nor column 1 (every slot
+  // is written before the panel's column 255), row-copy tag 0xFFFFFFFF no column
+  const int64_t ws_words = (int64_t)((slot_bytes + row_bytes + rowc_bytes) / sizeof(unsigned long long));
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((ws_words + 255) / 256)), dim3(256), 0, s, slot,
+                     ws_words, ~0ull);
   int rc = launch_status();
   for (int64_t j = 0; j < n && rc == 0; j += nb) {
     const int64_t jb = nb < n - j ? nb : n - j;

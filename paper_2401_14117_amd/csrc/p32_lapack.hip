@@ -522,7 +522,10 @@ trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t
   const uint32_t v0 = lane < w ? row[lane] : 0u;
   bool vnar = v0 == kNaR;
   win acc = lane < w ? bias(win_of(vnar ? 0u : v0)) : idle_acc();
+  int2 mnext = Ls[lane][0];                       // read one step ahead (LDS latency)
   for (int c = 0; c < w; ++c) {
+    const int2 m = mnext;
+    if (c + 1 < w) mnext = Ls[lane][c + 1];
     if (lane == c) {
       if (dg_bad) vnar = true;
       else if (!vnar) acc = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
@@ -533,7 +536,6 @@ trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t
     const bool xnar = __builtin_amdgcn_readlane((int)vnar, c) != 0;
     const dec dx = dec_of_win(unbias(xc));                 // x_c, wave-uniform
     if (lane > c && lane < w) {
-      const int2 m = Ls[lane][c];
       if (m.y == kScNaR || xnar) vnar = true;
       else if (!vnar && dx.s != 0) {                       // x_c = 0 changes nothing
         dec md;
@@ -568,13 +570,14 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
 // on the chain itself.
 constexpr int kTrsvBlock = 64;
 
+template <int kind>
 __global__ void __launch_bounds__(kTrsvBlock)
 trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
-                 int64_t nrhs, int64_t s, int bs, int kind) {
+                 int64_t nrhs, int64_t s, int bs) {
   __shared__ int2 coef[kTrsvBlock][kTrsvBlock + 1];
   __shared__ lut_t lut[256];
-  const bool forward = kind == 0 || kind == 2;
-  const bool unit = kind == 0;
+  constexpr bool forward = kind == 0 || kind == 2;
+  constexpr bool unit = kind == 0;
   const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
   // coef[r][u]: coefficient of the u-th column in solve order in row r,
@@ -583,7 +586,7 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
   // (kind 3: a column of M is), and all of a lane's loads are issued before
   // the first is decoded, so the staging waits on memory once, not per row.
   {
-    const bool trans = kind == 3;
+    constexpr bool trans = kind == 3;
     uint32_t mv[kTrsvBlock];
 #pragma unroll
     for (int a = 0; a < kTrsvBlock; ++a) {
@@ -618,8 +621,13 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
   win acc = lane < bs ? bias(win_of(xnar ? 0u : x0)) : idle_acc();   // biased window form
   for (int i = lane; i < 256; i += kTrsvBlock) lut[i] = make_lut_entry(i);
   __syncthreads();
+  // this lane's coefficient of the next step, read one step ahead so that the
+  // LDS latency stays off the chain
+  int2 mnext = coef[lane][0];
   for (int u = 0; u < bs; ++u) {
     const int cl = forward ? u : bs - 1 - u;                // local column (wave-uniform)
+    const int2 m = mnext;
+    if (u + 1 < bs) mnext = coef[lane][u + 1];
     if (!unit && lane == cl) {
       if (dg_bad) xnar = true;
       else if (!xnar) acc = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
@@ -631,7 +639,6 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
     const dec dx = dec_of_win(unbias(pc));                 // x[c], wave-uniform
     const bool below = forward ? lane > cl : lane < cl;
     if (lane < bs && below) {
-      const int2 m = coef[lane][u];
       if (m.y == kScNaR || pnar) xnar = true;
       else if (!xnar && dx.s != 0) {                       // x[c] = 0 changes nothing
         dec md;
@@ -731,8 +738,11 @@ static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t s0 = forward ? b * bsz : (nblk - 1 - b) * bsz;
     const int64_t bs = s0 + bsz < n ? bsz : n - s0;
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3((unsigned)nrhs), dim3(kTrsvBlock), 0, s, M, lda, B, ldb,
-                       nrhs, s0, (int)bs, kind);
+    const dim3 grid((unsigned)nrhs), block(kTrsvBlock);
+    if (kind == 0) hipLaunchKernelGGL(trsv_diag_kernel<0>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else if (kind == 1) hipLaunchKernelGGL(trsv_diag_kernel<1>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else if (kind == 2) hipLaunchKernelGGL(trsv_diag_kernel<2>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else hipLaunchKernelGGL(trsv_diag_kernel<3>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
     const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? n : s0;
     if (r1 > r0) {
       const unsigned gy = (unsigned)(nrhs < 65535 ? nrhs : 65535);

@@ -552,7 +552,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU Rgemm is a design "
+        print("bench.py: measures one GPU only; the multi-GPU Rgemm is a design "
               "(row blocks of C per GPU, one broadcast of B) and is not implemented",
               file=sys.stderr)
         return 2

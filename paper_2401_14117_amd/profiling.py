@@ -24,6 +24,10 @@ import json
 import os
 
 
+WHERE = ("run on the MI355X box from /tmp, REPO = the repository root, "
+         "OUT = the directory the profiler writes to")
+
+
 def _one(d: str, suffix: str) -> str:
     files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
     if not files:
@@ -72,18 +76,18 @@ def summarize(args) -> None:
         f"Workload: {args.workload} (m = {m}, n = {n}, k = {k}).",
         f"Kernel source hash: {args.kernel_hash}.",
         "",
-        "Commands (run on the MI355X box from /tmp, REPO = the repository root):",
+        "Commands (" + WHERE + "):",
         "",
         "```",
-        f"rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof/trace -o trace -- "
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o trace -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 2 --warmup 1 --cpu-budget 0",
-        f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/fetch -o fetch -- "
+        f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/fetch -o fetch -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
-        f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/write -o write -- "
+        f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/write -o write -- "
         f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
-        "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/copyf -o copyf -- "
+        "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/copyf -o copyf -- "
         "python3 $REPO/bench.py --copy-calibration",
-        "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $REPO/gpurun_out/prof/copyw -o copyw -- "
+        "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/copyw -o copyw -- "
         "python3 $REPO/bench.py --copy-calibration",
         "```",
         "",
@@ -126,8 +130,7 @@ def kernel_table(args) -> None:
     stats = kernel_stats(args.trace)
     rows = sorted(((c * a, k, c, a) for k, (c, a) in stats.items()), reverse=True)
     total = sum(r[0] for r in rows)
-    lines = [f"# rocprofv3: {args.title}", "", "Command (run on the MI355X box from /tmp, REPO = the "
-             "repository root):", "", "```", args.command, "```", "",
+    lines = [f"# rocprofv3: {args.title}", "", "Command (" + WHERE + "):", "", "```", args.command, "```", "",
              f"Kernel time in the traced run: {total / 1e6:.2f} ms.", "",
              "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
     for tot, k, c, a in rows[:args.top]:
@@ -150,9 +153,9 @@ def valu_table(args) -> None:
     cycles = avg_ns * 1e-9 * args.clock_ghz * 1e9
     lines = [f"# rocprofv3: VALU utilisation of the Posit(32,2) Rgemm kernel, {args.workload}", "",
              f"Kernel: `{name}`", f"Kernel source hash: {args.kernel_hash}.", "",
-             "Commands (run on the MI355X box from /tmp, REPO = the repository root):", "", "```",
+             "Commands (" + WHERE + "):", "", "```",
              f"rocprofv3 --pmc {' '.join(args.counters)} --kernel-trace --output-format csv "
-             f"-d $REPO/gpurun_out/prof/valu -o valu -- python3 $REPO/bench.py --workload {args.workload} "
+             f"-d $OUT/valu -o valu -- python3 $REPO/bench.py --workload {args.workload} "
              "--steps 1 --warmup 0 --cpu-budget 0",
              "(kernel duration from the --kernel-trace --stats run of the Rgemm summary)", "```", "",
              "| counter (per dispatch, summed over the chip) | value |", "|---|---|"]

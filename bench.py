@@ -15,7 +15,10 @@ import argparse
 import hashlib
 import json
 import os
+import re
+import subprocess
 import sys
+import threading
 import time
 
 import numpy as np
@@ -138,6 +141,50 @@ def run_elementwise_bench(name: str, args, dev) -> dict:
     }
 
 
+def _socket_power_w() -> float | None:
+    """GPU package power in watts as amd-smi reports it (None when unavailable)."""
+    try:
+        out = subprocess.run(["amd-smi", "metric", "-p"], capture_output=True, text=True,
+                             timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    m = re.search(r"SOCKET_POWER:\s*([0-9.]+)\s*W", out)
+    return float(m.group(1)) if m else None
+
+
+def _power_while(step, seconds: float) -> dict | None:
+    """Mean GPU package power while `step` runs back to back for `seconds`
+    (amd-smi sampled from a second thread), with the idle reading before."""
+    import torch
+    idle = _socket_power_w()
+    if idle is None or seconds <= 0:
+        return None
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            w = _socket_power_w()
+            if w is not None:
+                samples.append(w)
+            stop.wait(0.2)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
+    t_end, runs = time.perf_counter() + seconds, 0
+    while time.perf_counter() < t_end:
+        step()
+        torch.cuda.synchronize()
+        runs += 1
+    stop.set()
+    th.join()
+    # the first sample may predate the load
+    busy = samples[1:] if len(samples) > 2 else samples
+    if not busy:
+        return None
+    return {"socket_w_idle": idle, "socket_w_mean": round(float(np.mean(busy)), 1),
+            "samples": len(busy), "runs": runs, "seconds": seconds}
+
+
 def run_solve_bench(name: str, args, dev) -> dict:
     """Factor + solve workloads (getrf_nN / potrf_nN): one step = copy the
     matrix into the work buffer, factor it, solve A x = b (nrhs = 1)."""
@@ -193,16 +240,27 @@ def run_solve_bench(name: str, args, dev) -> dict:
                            case.b[:, 0].astype(np.float32))
     err = float(np.linalg.norm(x - x64) / np.linalg.norm(x64))
     err32 = float(np.linalg.norm(x32.astype(np.float64) - x64) / np.linalg.norm(x64))
+    value = pops / (ms_per_step * 1e-3) / 1e9
+    # GPU package power over repeated factor + solve runs (after the timed
+    # region); the paper's LU figure is whole-system AC power, so it is context
+    power = _power_while(step, args.power_seconds)
+    if power is not None:
+        power["source"] = "amd-smi metric -p, SOCKET_POWER (GPU package only)"
+        power["gpops_per_w"] = round(value / power["socket_w_mean"], 3)
+        if kind == "getrf":
+            power["paper_lu_gflops_per_w"] = ("0.043-0.076: whole-system AC power, LU at N = 8000 on "
+                                              "an FPGA and three GPUs (Sec. 5.3, Table 6)")
     return {
         "metric": f"Posit32 R{kind} + R{kind[:3]}rs Gpops/s (factor {'2' if kind == 'getrf' else '1'}n^3/3 pops)",
-        "value": round(pops / (ms_per_step * 1e-3) / 1e9, 3),
+        "value": round(value, 3),
         "unit": "Gpops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "posit32 (int32 VALU)", "data": "synthetic",
         "config": {"workload": case.name, "n": n, "nb": args.nb, "nrhs": 1,
                    "factor_solve_ms_events": round(kms, 3), "info": int(info.cpu().item()),
                    "forward_error_posit32": err, "forward_error_binary32": err32,
-                   "digits_gained_vs_binary32": round(float(np.log10(err32 / err)), 3)},
+                   "digits_gained_vs_binary32": round(float(np.log10(err32 / err)), 3),
+                   "power": power},
         "roofline": None, "cpu_baseline": None,
     }
 
@@ -540,6 +598,9 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=20000, help="systems of the batched workloads")
     ap.add_argument("--qps", type=float, nargs="+", default=[25.0, 50.0, 100.0, 150.0],
                     help="arrival rates of the serving workload (requests per second)")
+    ap.add_argument("--power-seconds", type=float, default=8.0,
+                    help="factor + solve workloads: seconds of repeated runs while GPU package power "
+                         "is sampled with amd-smi (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each arrival stream of the serving workload")
     ap.add_argument("--single-count", type=int, default=300,

@@ -444,7 +444,7 @@ def run_serve_bench(args, dev) -> list[dict]:
                 Ap = posit32.from_f64(torch.from_numpy(A).to(dev)).cpu().numpy().view(np.uint32)
                 Bp = posit32.from_f64(torch.from_numpy(B).to(dev)).cpu().numpy().view(np.uint32)
                 payload[k] = (Ap, Bp)
-        q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=512)
+        q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=args.batch_max_n)
         # warm-up: one small and one large system
         for k in (64, 1024):
             A, B = W.serve_system(k, 2, 7001)
@@ -482,7 +482,7 @@ def run_serve_bench(args, dev) -> list[dict]:
             "data": "synthetic",
             "config": {"workload": "serve_lu", "qps": qps, "requests": int(len(n)),
                        "seconds": args.serve_seconds, "n": "round(exp(U(ln 32, ln 2048)))",
-                       "nrhs": "1..32", "batch_max_n": 512,
+                       "nrhs": "1..32", "batch_max_n": args.batch_max_n,
                        "p50_ms": round(float(np.percentile(lat, 50)), 2),
                        "p99_ms": round(float(np.percentile(lat, 99)), 2),
                        "p50_ms_small_n": round(float(np.percentile(lat[small], 50)), 2) if small.any() else None,
@@ -504,7 +504,7 @@ def _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev) -> dict:
     the served one bit for bit."""
     import torch
     from paper_2401_14117_amd import posit32
-    q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=512)
+    q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=args.batch_max_n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = [q.submit(posit32.REQ_LU, payload[int(k)][1][:, :int(r)], payload[int(k)][0])
@@ -601,6 +601,8 @@ def main() -> int:
     ap.add_argument("--power-seconds", type=float, default=8.0,
                     help="factor + solve workloads: seconds of repeated runs while GPU package power "
                          "is sampled with amd-smi (0: skip)")
+    ap.add_argument("--batch-max-n", type=int, default=512,
+                    help="serving workload: largest n the queue sends through the batched kernels")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each arrival stream of the serving workload")
     ap.add_argument("--single-count", type=int, default=300,

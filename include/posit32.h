@@ -289,9 +289,11 @@ int posit32_vbatched_default_tuning(int kind, posit32_vbatch_tuning* out);
  *    to 256) fits the pool.
  *  - Whenever fewer than two batches are in flight, the worker launches every
  *    admitted waiting request (up to cfg->max_batch) as one batch: systems with
- *    n <= cfg->batch_max_n through the batched kernels, larger ones through
- *    the single-matrix routines; host-to-device copies overlap the previous
- *    batch's computation.
+ *    n <= cfg->batch_max_n / 2 through the batched kernels, and those with
+ *    n <= cfg->batch_max_n too when at least four of them are in the batch
+ *    (alone, such a system is faster through the single-matrix routines);
+ *    the others through the single-matrix routines.  Host-to-device copies
+ *    overlap the previous batch's computation.
  *  - Each system is factored and solved exactly as posit32_gesv_vbatched /
  *    posit32_posv_vbatched (or the single-matrix calls) with block size
  *    cfg->nb would do it: the solution is bit-identical however requests are
@@ -326,7 +328,7 @@ typedef struct {
   int64_t device_bytes;      /* device pool for admitted systems and resident factors */
   int32_t max_batch;         /* most systems per batch */
   int32_t nb;                /* block size of the factorisations */
-  int32_t batch_max_n;       /* largest n sent through the batched kernels */
+  int32_t batch_max_n;       /* largest n sent through the batched kernels (see above) */
   const posit32_vbatch_tuning* tuning;   /* NULL, or [LU, Cholesky] tables */
 } posit32_queue_cfg;
 

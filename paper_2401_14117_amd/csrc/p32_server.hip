@@ -13,8 +13,10 @@
 //   * continuous batching: whenever fewer than two batches are in flight, the
 //     worker takes every admitted request that is waiting (up to max_batch)
 //     and launches it as one batch, without waiting for a batch to fill:
-//     systems with n <= batch_max_n go through the batched kernels (one launch
-//     per kind), larger ones through the single-matrix routines;
+//     systems with n <= batch_max_n / 2 go through the batched kernels (one
+//     launch per kind), and so do those with n <= batch_max_n when at least
+//     kMidShare of them are in the batch; the others go through the
+//     single-matrix routines;
 //   * overlap: a batch's host-to-device copies run on a copy stream while the
 //     previous batch computes on the compute stream; results come back on the
 //     compute stream and are copied out when its event completes;
@@ -44,6 +46,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kSlots = 2;                    // batches in flight
+// A system with batch_max_n / 2 < n <= batch_max_n takes longer in one
+// workgroup of the batched kernel than alone through the single-matrix
+// routines (n = 512: about 20 ms against 5 ms), unless several of them share
+// a batch and run side by side; they join the batched launch only when at
+// least this many of them are in the batch.
+constexpr size_t kMidShare = 4;
 
 size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
@@ -259,11 +267,14 @@ int start_batch(posit32_queue* q, Slot& s) {
   std::vector<Req*>& rs = s.reqs;
   // largest systems first: the batched kernel hands systems out round-robin
   std::stable_sort(rs.begin(), rs.end(), [](const Req* a, const Req* b) { return a->n > b->n; });
-  const int64_t small_max = q->cfg.batch_max_n;
+  const int64_t small_max = q->cfg.batch_max_n, mid_min = small_max / 2;
+  size_t mid = 0;
+  for (const Req* r : rs) mid += r->n > mid_min && r->n <= small_max;
+  const int64_t batched_max = mid >= kMidShare ? small_max : mid_min;
   // groups: 0 LU new, 1 Cholesky new, 2 LU resident, 3 Cholesky resident (batched)
   std::vector<Req*> groups[4], large;
   for (Req* r : rs) {
-    if (r->n > small_max) large.push_back(r);
+    if (r->n > batched_max) large.push_back(r);
     else groups[(r->factor_in ? 2 : 0) + r->kind].push_back(r);
   }
   // packed inputs

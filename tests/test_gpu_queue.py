@@ -83,6 +83,29 @@ def test_queue_mixed_requests_bitwise(P):
     assert st["systems_done"] == len(reqs) and st["pool_used"] == 0 and st["error"] == 0
 
 
+def test_queue_mid_size_burst_bitwise(P):
+    """A burst of systems with batch_max_n / 2 < n <= batch_max_n: whether a
+    batch sends them through the batched kernel (four or more of them) or
+    through the single-matrix routines (fewer), each solution equals the
+    system solved alone."""
+    rng = np.random.default_rng(23)
+    sizes = [300, 480, 257, 512, 400, 333, 290]
+    reqs = []
+    for i, n in enumerate(sizes):
+        kind = i % 2
+        A = _lu(rng, n) if kind == 0 else _spd(rng, n)
+        reqs.append((kind, A, p32(rng.uniform(-1, 1, (n, 2)))))
+    q = P.Queue(device_bytes=256 << 20, max_batch=64, nb=256, batch_max_n=512)
+    tickets = [q.submit(kind, B, A) for kind, A, B in reqs]
+    outs = [q.wait(t, 120.0) for t in tickets]
+    q.close()
+    for (kind, A, B), out in zip(reqs, outs):
+        assert out is not None and out["status"] == 0 and out["info"] == 0
+        X, info = _alone(P, kind, A, B)
+        assert info == 0
+        assert np.array_equal(out["X"], X), (kind, A.shape[0])
+
+
 def test_queue_matches_oracle(P):
     rng = np.random.default_rng(22)
     q = P.Queue(device_bytes=64 << 20)

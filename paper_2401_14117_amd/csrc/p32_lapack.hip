@@ -12,7 +12,7 @@
 //    update of the panel's remaining columns), the rows spread over the
 //    workgroups and the pivot candidates exchanged through per-workgroup
 //    slots; then the interchanges go to the other columns, U12 = L11^-1 A12
-//    (one wave per column of A12) and A22 = Rgemm(-1, 1, L21, U12).
+//    (one workgroup per column of A12) and A22 = Rgemm(-1, 1, L21, U12).
 //  Rpotrf, per diagonal block, kCholSub columns at a time: the sub-block's
 //    unblocked Cholesky in one workgroup, every row below it solved against
 //    its triangle (one wave per row), and a fused-update chain over its
@@ -23,6 +23,8 @@
 //  Rgetrs / Rpotrs: blocked triangular solves -- a diagonal block solved by
 //    one workgroup per right-hand side, then the rows outside it updated in
 //    parallel, applying the block's columns in the stated order.
+// The single fused updates of these unblocked steps take the Rgemm tile's
+// k-step arithmetic where it is proven exact (chain_update, p32_chain.hpp).
 #include <hip/hip_runtime.h>
 
 #include "p32_chain.hpp"

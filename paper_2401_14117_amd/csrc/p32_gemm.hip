@@ -35,6 +35,34 @@ namespace p32 {
 
 // One tile per workgroup.  skip: when non-null and nonzero on entry, the
 // kernel does nothing (a failed factorisation step).
+// Tiles of a LOWER launch: only the tiles that reach the lower triangle (row
+// >= column somewhere in the tile), band by band: band bi (rows 64 bi ..)
+// reaches the column tiles 0 .. 2 bi + 1 (BM = 2 BN).  The sequence is cut
+// into eight equal chunks, one per XCD as in tile_origin, so every XCD gets
+// the same number of tiles; cutting the full rectangle into chunks of bands
+// instead would give the bottom band's XCD about fifteen times the work of
+// the top one's.
+static_assert(BM == 2 * BN, "lower-triangle tile count assumes 64 x 32 tiles");
+__host__ __device__ inline int64_t lower_tiles_before(int64_t band, int64_t ncol) {
+  const int64_t t = ncol / 2;                    // bands b < t reach 2 b + 2 <= ncol tiles
+  return band <= t ? band * (band + 1) : t * (t + 1) + (band - t) * ncol;
+}
+
+__device__ __forceinline__ void lower_tile_origin(int64_t m, int64_t n, unsigned g, int64_t& i0,
+                                                  int64_t& j0) {
+  const int64_t nrow = (m + BM - 1) / BM, ncol = (n + BN - 1) / BN;
+  const int64_t G = lower_tiles_before(nrow, ncol);
+  if (G % 8 == 0) g = (unsigned)((g % 8u) * (G / 8) + g / 8u);
+  int64_t lo = 0, hi = nrow - 1;                 // largest band whose first tile is <= g
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (lower_tiles_before(mid, ncol) <= (int64_t)g) lo = mid;
+    else hi = mid - 1;
+  }
+  i0 = lo * BM;
+  j0 = ((int64_t)g - lower_tiles_before(lo, ncol)) * BN;
+}
+
 template <bool TA, bool TB, bool LOWER, bool CHAIN>
 __global__ void __launch_bounds__(NT, P32_GEMM_MIN_WAVES)
 gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
@@ -43,7 +71,8 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
   __shared__ TileLds sm;
   if (skip != nullptr && *skip != 0) return;
   int64_t i0, j0;
-  tile_origin(m, n, blockIdx.x, i0, j0);
+  if (LOWER) lower_tile_origin(m, n, blockIdx.x, i0, j0);
+  else tile_origin(m, n, blockIdx.x, i0, j0);
   gemm_tile<TA, TB, LOWER, CHAIN>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, i0, j0, sm);
 }
 
@@ -73,7 +102,8 @@ int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t 
                        lower, skip);
     return launch_status();
   }
-  const int64_t tiles = ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
+  const int64_t tiles = lower ? lower_tiles_before((m + BM - 1) / BM, (n + BN - 1) / BN)
+                              : ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
   if (tiles * NT >= ((int64_t)1 << 32)) return -4;   // beyond one 1-D launch
   const dim3 grid((unsigned)tiles);
   const dim3 block(NT);
@@ -95,7 +125,8 @@ int launch_fms_chain(hipStream_t s, int tb, int64_t m, int64_t n, int64_t k, con
                      int64_t lda, const uint32_t* B, int64_t ldb, uint32_t* C, int64_t ldc, bool lower,
                      const int32_t* skip) {
   if (m == 0 || n == 0 || k == 0) return 0;
-  const int64_t tiles = ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
+  const int64_t tiles = lower ? lower_tiles_before((m + BM - 1) / BM, (n + BN - 1) / BN)
+                              : ((n + BN - 1) / BN) * ((m + BM - 1) / BM);
   if (tiles * NT >= ((int64_t)1 << 32)) return -4;
   const dim3 grid((unsigned)tiles);
   const dim3 block(NT);

@@ -179,3 +179,61 @@ def test_solves_with_nar_and_zero_diagonal(P, n, nrhs, where):
     Bd = to_dev(B)
     P.potrs(to_dev(M), Bd)
     assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+
+
+def _perm(ipiv):
+    """Row order of P A for LAPACK-style interchanges applied in order."""
+    perm = np.arange(len(ipiv))
+    for c, p in enumerate(ipiv):
+        perm[c], perm[p] = perm[p], perm[c]
+    return perm
+
+
+# Posit(32,2) unit roundoff for |x| in [2^-12, 2^12): at least 25 fraction
+# bits, so a rounding's relative error is at most 2^-26.
+U_POSIT = 2.0 ** -26
+
+
+@pytest.mark.parametrize("n", [4096, 8192])
+def test_getrf_full_size_backward_error(P, n):
+    """The benchmark's LU (uniform[-1,1], nb = 256) at its full sizes, where
+    the oracle is too slow: info = 0, pivots in range, and P A = L U within
+    the componentwise bound of Gaussian elimination, |P A - L U| <= n u |L||U|
+    (a wrong pivot or update would miss it by orders of magnitude)."""
+    import torch
+    case = W.lu_case(n)
+    A = P.from_f64(torch.from_numpy(case.A).cuda())
+    LU = A.clone()
+    _, ipiv, info = P.getrf(LU, 256)
+    assert int(info.item()) == 0
+    piv = ipiv.cpu().numpy()
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    F = P.to_f64(LU)
+    eye = torch.eye(n, dtype=torch.float64, device=F.device)
+    L = torch.tril(F, -1) + eye
+    U = torch.triu(F)
+    PA = P.to_f64(A)[torch.from_numpy(_perm(piv)).cuda()]
+    R = (PA - L @ U).abs()
+    bound = n * U_POSIT * (L.abs() @ U.abs())
+    ratio = float((R / bound.clamp_min(1e-300)).max())
+    print(f"n = {n}: max |residual| / bound = {ratio:.3e}")
+    assert ratio <= 1.0, ratio
+
+
+@pytest.mark.parametrize("n", [4096, 8192])
+def test_potrf_full_size_backward_error(P, n):
+    """The benchmark's Cholesky (A = B B^T / n + I, nb = 256) at its full
+    sizes: info = 0 and A = L L^T within |A - L L^T| <= (n + 1) u |L||L^T|
+    on the lower triangle."""
+    import torch
+    case = W.chol_case(n)
+    A = P.from_f64(torch.from_numpy(case.A).cuda())
+    Lp = A.clone()
+    _, info = P.potrf(Lp, 256)
+    assert int(info.item()) == 0
+    L = torch.tril(P.to_f64(Lp))
+    R = torch.tril(P.to_f64(A) - L @ L.T.contiguous()).abs()
+    bound = torch.tril((n + 1) * U_POSIT * (L.abs() @ L.abs().T.contiguous()))
+    ratio = float((R / bound.clamp_min(1e-300)).max())
+    print(f"n = {n}: max |residual| / bound = {ratio:.3e}")
+    assert ratio <= 1.0, ratio

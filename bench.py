@@ -315,15 +315,33 @@ def run_batch_bench(name: str, args, dev) -> dict:
     setup_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
 
+    def launch():
+        if kind == "lu":
+            vb.gesv(args.nb)
+        else:
+            vb.posv(args.nb)
+
+    # the eager launch once (the reference for the graph's results), then the
+    # launch captured in a hipGraph; each timed step replays the graph
+    A.copy_(A0)
+    B.copy_(B0)
+    launch()
+    torch.cuda.synchronize()
+    eager_B, eager_info = B.clone(), vb.info.clone()
+    A.copy_(A0)
+    B.copy_(B0)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        launch()
+    torch.cuda.synchronize()
+
     def step(ev0=None, ev1=None):
         A.copy_(A0)
         B.copy_(B0)
         if ev0 is not None:
             ev0.record(stream)
-        if kind == "lu":
-            vb.gesv(args.nb)
-        else:
-            vb.posv(args.nb)
+        graph.replay()
         if ev1 is not None:
             ev1.record(stream)
 
@@ -337,12 +355,13 @@ def run_batch_bench(name: str, args, dev) -> dict:
     torch.cuda.synchronize()
     kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     info = vb.info.cpu().numpy()
+    graph_same = bool(torch.equal(B, eager_B) and torch.equal(vb.info, eager_info))
     fac = (2.0 if kind == "lu" else 1.0) / 3.0
     pops = float(np.sum(fac * n.astype(np.float64) ** 3))
 
     # one system at a time through the single-matrix entry points, on a sample
     if args.single_count <= 0:
-        return _batch_result(name, kind, count, kms, pops, info, setup_s, None, None, args)
+        return _batch_result(name, kind, count, kms, pops, info, setup_s, None, None, args, graph_same)
     rs = np.random.default_rng(6001)
     sample = np.sort(rs.choice(count, size=min(args.single_count, count), replace=False))
     A.copy_(A0)
@@ -396,7 +415,7 @@ def run_batch_bench(name: str, args, dev) -> dict:
         cpu = {"value": round(done / el, 3), "unit": "solves/s", "cores": O.num_threads(),
                "kind": "oracle", "sample": f"first {done} systems of the batch (in generation order)"}
 
-    return _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args)
+    return _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args, graph_same)
 
 
 def _tuning_info(kind: str) -> dict:
@@ -408,7 +427,7 @@ def _tuning_info(kind: str) -> dict:
     return {"source": os.path.relpath(src, ROOT) if src != "built-in" else src, **t.to_dict()}
 
 
-def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args) -> dict:
+def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args, graph_same) -> dict:
     return {
         "metric": f"Posit32 batched {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s",
         "value": round(count / (kms * 1e-3), 1),
@@ -418,7 +437,9 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
         "config": {"workload": name, "count": count, "n": "round(exp(U(ln 16, ln 512)))",
                    "nrhs": "1..16", "nb": args.nb, "factor_gpops": round(pops / (kms * 1e-3) / 1e9, 1),
                    "info_nonzero": int(np.count_nonzero(info)), "setup_s": round(setup_s, 1),
-                   "sub_panel_tuning": _tuning_info(kind), "one_at_a_time": single},
+                   "sub_panel_tuning": _tuning_info(kind),
+                   "launch": "one persistent kernel captured in a hipGraph; each step is a replay",
+                   "graph_bit_identical_to_eager": graph_same, "one_at_a_time": single},
         "roofline": None,
         "cpu_baseline": cpu,
     }

@@ -445,33 +445,35 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
     }
 
 
-def run_serve_bench(args, dev) -> list[dict]:
-    """serve_lu: the request queue under Poisson arrivals, one JSON line per
-    arrival rate.  Each request is a new LU system (n log-uniform in [32, 2048],
-    nrhs in [1, 32]); its latency is completion minus submission on the queue's
-    own clock.  Payloads are converted to posit patterns before the clock
-    starts; requests of the same n share one system (B's first nrhs columns)."""
+def run_serve_bench(args, dev, kind: str = "lu") -> list[dict]:
+    """serve_lu / serve_chol: the request queue under Poisson arrivals, one
+    JSON line per arrival rate.  Each request is a new LU (or Cholesky) system
+    (n log-uniform in [32, 2048], nrhs in [1, 32]); its latency is completion
+    minus submission on the queue's own clock.  Payloads are converted to
+    posit patterns before the clock starts; requests of the same n share one
+    system (B's first nrhs columns)."""
     import threading
     import torch
     from paper_2401_14117_amd import posit32
     from paper_2401_14117_amd import workloads as W
     lines = []
     payload = {}                                   # n -> (A, B with 32 columns)
+    req = posit32.REQ_LU if kind == "lu" else posit32.REQ_CHOL
     for qps in args.qps:
         t_arr, n, nrhs = W.serve_stream(qps, args.serve_seconds)
         for k in n.tolist():
             if k not in payload:
-                A, B = W.serve_system(k, 32, 7000)
+                A, B = W.serve_system(k, 32, 7000, kind)
                 Ap = posit32.from_f64(torch.from_numpy(A).to(dev)).cpu().numpy().view(np.uint32)
                 Bp = posit32.from_f64(torch.from_numpy(B).to(dev)).cpu().numpy().view(np.uint32)
                 payload[k] = (Ap, Bp)
         q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=args.batch_max_n)
         # warm-up: one small and one large system
         for k in (64, 1024):
-            A, B = W.serve_system(k, 2, 7001)
+            A, B = W.serve_system(k, 2, 7001, kind)
             Ap = posit32.from_f64(torch.from_numpy(A).to(dev)).cpu().numpy().view(np.uint32)
             Bp = posit32.from_f64(torch.from_numpy(B).to(dev)).cpu().numpy().view(np.uint32)
-            q.wait(q.submit(posit32.REQ_LU, Bp, Ap), 120.0)
+            q.wait(q.submit(req, Bp, Ap), 120.0)
         tickets = [None] * len(n)
         t0 = time.perf_counter()
 
@@ -481,7 +483,7 @@ def run_serve_bench(args, dev) -> list[dict]:
                 if delay > 0:
                     time.sleep(delay)
                 Ap, Bp = payload[int(n[i])]
-                tickets[i] = q.submit(posit32.REQ_LU, Bp[:, :int(nrhs[i])], Ap)
+                tickets[i] = q.submit(req, Bp[:, :int(nrhs[i])], Ap)
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -489,19 +491,20 @@ def run_serve_bench(args, dev) -> list[dict]:
         outs = [q.wait(t, 600.0) for t in tickets]
         st = q.stats()
         q.close()
-        single = _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev) \
+        single = _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev, kind) \
             if qps == args.qps[-1] else None
         lat = np.array([o["done_s"] - o["submit_s"] for o in outs]) * 1e3
         span = max(o["done_s"] for o in outs) - min(o["submit_s"] for o in outs)
         bad = sum(1 for o in outs if o["status"] != 0 or o["info"] != 0)
         small = n <= 512
         lines.append({
-            "metric": "Posit32 served LU factor+solve solves/s (Poisson arrivals, p50/p99 latency)",
+            "metric": f"Posit32 served {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s "
+                      "(Poisson arrivals, p50/p99 latency)",
             "value": round(len(n) / span, 1), "unit": "solves/s", "n_gpus": 1,
             "steps": 1, "warmup": 2, "ms_per_step": round(span * 1e3, 1), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "posit32 (int32 VALU)",
             "data": "synthetic",
-            "config": {"workload": "serve_lu", "qps": qps, "requests": int(len(n)),
+            "config": {"workload": f"serve_{kind}", "qps": qps, "requests": int(len(n)),
                        "seconds": args.serve_seconds, "n": "round(exp(U(ln 32, ln 2048)))",
                        "nrhs": "1..32", "batch_max_n": args.batch_max_n,
                        "p50_ms": round(float(np.percentile(lat, 50)), 2),
@@ -510,25 +513,27 @@ def run_serve_bench(args, dev) -> list[dict]:
                        "p99_ms_small_n": round(float(np.percentile(lat[small], 99)), 2) if small.any() else None,
                        "mean_batch": round(st["systems_done"] / max(st["batches"], 1), 2),
                        "failed": bad, "factor_gpops": round(
-                           float(np.sum(2.0 * n.astype(np.float64) ** 3 / 3)) / span / 1e9, 1),
+                           float(np.sum((2.0 if kind == "lu" else 1.0) * n.astype(np.float64) ** 3 / 3))
+                           / span / 1e9, 1),
                        "same_requests": single},
             "roofline": None, "cpu_baseline": None,
         })
     return lines
 
 
-def _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev) -> dict:
+def _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev, kind) -> dict:
     """The last rate's requests two more ways: all submitted at once to a new
     queue (its throughput with no arrival gaps), and one after another with
-    the single-matrix calls (host -> device copy, getrf, getrs, copy back), the
-    baseline the queue is compared with.  Every solution of both must equal
-    the served one bit for bit."""
+    the single-matrix calls (host -> device copy, getrf + getrs or potrf +
+    potrs, copy back), the baseline the queue is compared with.  Every
+    solution of both must equal the served one bit for bit."""
     import torch
     from paper_2401_14117_amd import posit32
     q = posit32.Queue(device_bytes=8 << 30, max_batch=1024, nb=args.nb, batch_max_n=args.batch_max_n)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tickets = [q.submit(posit32.REQ_LU, payload[int(k)][1][:, :int(r)], payload[int(k)][0])
+    req = posit32.REQ_LU if kind == "lu" else posit32.REQ_CHOL
+    tickets = [q.submit(req, payload[int(k)][1][:, :int(r)], payload[int(k)][0])
                for k, r in zip(n, nrhs)]
     burst = [q.wait(t, 600.0) for t in tickets]
     burst_s = time.perf_counter() - t0
@@ -541,8 +546,12 @@ def _serve_burst_vs_one_at_a_time(payload, n, nrhs, outs, args, dev) -> dict:
         Ap, Bp = payload[int(n[i])]
         A = torch.from_numpy(Ap.view(np.int32)).to(dev)
         B = torch.from_numpy(np.ascontiguousarray(Bp[:, :int(nrhs[i])]).view(np.int32)).to(dev)
-        _, ipiv, _ = posit32.getrf(A, args.nb)
-        posit32.getrs(A, ipiv, B)
+        if kind == "lu":
+            _, ipiv, _ = posit32.getrf(A, args.nb)
+            posit32.getrs(A, ipiv, B)
+        else:
+            posit32.potrf(A, args.nb)
+            posit32.potrs(A, B)
         X = B.cpu().numpy().view(np.uint32)
         same = same and np.array_equal(X, outs[i]["X"])
     single_s = time.perf_counter() - t0
@@ -611,7 +620,7 @@ def main() -> int:
     ap.add_argument("--workload", default="square_n8192",
                     help="square_nN | trailing_jJ | uniform_nN | normal_sigmaS_nN (Rgemm), "
                          "getrf_nN | potrf_nN (factor+solve), batch_lu | batch_chol (batched "
-                         "factor+solve), serve_lu (request queue), ew_OP_IR | ew_all "
+                         "factor+solve), serve_lu | serve_chol (request queue), ew_OP_IR | ew_all "
                          "(elementwise, OP in add/mul/div/sqrt, R in 0..4)")
     ap.add_argument("--trans", default="nn", choices=["nn", "nt", "tn", "tt"],
                     help="Rgemm transposes op(A), op(B) (square workloads reuse the buffers)")
@@ -658,8 +667,8 @@ def main() -> int:
     if args.workload.startswith(("getrf_n", "potrf_n")):
         print(json.dumps(run_solve_bench(args.workload, args, dev)))
         return 0
-    if args.workload == "serve_lu":
-        for line in run_serve_bench(args, dev):
+    if args.workload in ("serve_lu", "serve_chol"):
+        for line in run_serve_bench(args, dev, args.workload[len("serve_"):]):
             print(json.dumps(line), flush=True)
         return 0
     if args.workload in ("batch_lu", "batch_chol"):

@@ -72,6 +72,10 @@ def lib() -> ctypes.CDLL:
             L.oracle_getrs.argtypes = [i64, i64, vp, i64, vp, vp, i64]
             L.oracle_potrf.argtypes = [i64, i64, vp, i64, vp]
             L.oracle_potrs.argtypes = [i64, i64, vp, i64, vp, i64]
+            L.oracle_getrs_trans.argtypes = [i64, i64, vp, i64, vp, vp, i64]
+            L.oracle_potrf_upper.argtypes = [i64, i64, vp, i64, vp]
+            L.oracle_potrf_upper.restype = i32
+            L.oracle_potrs_upper.argtypes = [i64, i64, vp, i64, vp, i64]
         _lib = L
     return _lib
 
@@ -217,32 +221,41 @@ def getrf(A, nb: int = 256):
     return A, ipiv, int(info[0])
 
 
-def getrs(LU, ipiv, B):
+def getrs(LU, ipiv, B, trans: bool = False):
+    """Solve A X = B (trans: A^T X = B) with the factors of getrf."""
     LU = np.ascontiguousarray(LU, dtype=np.uint32)
     ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
     X = np.array(B, dtype=np.uint32, copy=True, order="C")
     if X.ndim == 1:
         X = X.reshape(-1, 1)
     n = LU.shape[0]
-    lib().oracle_getrs(n, X.shape[1], _ptr(LU), n, _ptr(ipiv), _ptr(X), X.shape[1])
+    f = lib().oracle_getrs_trans if trans else lib().oracle_getrs
+    f(n, X.shape[1], _ptr(LU), n, _ptr(ipiv), _ptr(X), X.shape[1])
     return X
 
 
-def potrf(A, nb: int = 256):
-    """Blocked lower Cholesky (order in ref_lapack.c).  Returns (L, info);
-    only the lower triangle of L is meaningful, the rest is A's."""
+def potrf(A, nb: int = 256, upper: bool = False):
+    """Blocked Cholesky (order in ref_lapack.c).  Returns (L, info) (upper:
+    (U, info) with A = U^T U); only the factor's triangle is meaningful, the
+    rest is A's."""
     A = np.array(A, dtype=np.uint32, copy=True, order="C")
     n = A.shape[0]
     info = np.zeros(1, dtype=np.int32)
-    lib().oracle_potrf(n, nb, _ptr(A), n, _ptr(info))
+    if upper:
+        if lib().oracle_potrf_upper(n, nb, _ptr(A), n, _ptr(info)) != 0:
+            raise MemoryError("oracle_potrf_upper: no memory for the transposed copy")
+    else:
+        lib().oracle_potrf(n, nb, _ptr(A), n, _ptr(info))
     return A, int(info[0])
 
 
-def potrs(L, B):
+def potrs(L, B, upper: bool = False):
+    """Solve A X = B with the factor of potrf (upper: U with A = U^T U)."""
     L = np.ascontiguousarray(L, dtype=np.uint32)
     X = np.array(B, dtype=np.uint32, copy=True, order="C")
     if X.ndim == 1:
         X = X.reshape(-1, 1)
     n = L.shape[0]
-    lib().oracle_potrs(n, X.shape[1], _ptr(L), n, _ptr(X), X.shape[1])
+    f = lib().oracle_potrs_upper if upper else lib().oracle_potrs
+    f(n, X.shape[1], _ptr(L), n, _ptr(X), X.shape[1])
     return X

@@ -77,6 +77,12 @@ void oracle_potrf(int64_t n, int64_t nb, uint32_t* A, int64_t lda,
                   int32_t* info);
 void oracle_potrs(int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda,
                   uint32_t* B, int64_t ldb);
+/* the transposed solve and the upper Cholesky forms (order in ref_lapack.c) */
+void oracle_getrs_trans(int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+                        const int32_t* ipiv, uint32_t* B, int64_t ldb);
+int oracle_potrf_upper(int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info);
+void oracle_potrs_upper(int64_t n, int64_t nrhs, const uint32_t* U, int64_t lda, uint32_t* B,
+                        int64_t ldb);
 
 /* number of OpenMP threads the oracle's parallel loops use */
 int oracle_num_threads(void);

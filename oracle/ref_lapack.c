@@ -38,7 +38,23 @@
  *   b[r] - rnd(L[r][c] * b[c]); backward L^T: for c descending,
  *   b[c] = b[c] / L[c][c], rows r < c get b[r] - rnd(L[c][r] * b[c]).
  * Only the lower triangle of A is referenced or written by Rpotrf/Rpotrs.
+ *
+ * The transposed and upper forms (LAPACK's trans = 'T' and uplo = 'U'):
+ * Rgetrs with op = T solves A^T X = B.  P A = L U gives A^T = U^T L^T P, so:
+ *   forward U^T: for c ascending, b[c] = b[c] / U[c][c], rows r > c get
+ *   b[r] - rnd(U[c][r] * b[c]); backward L^T (unit): for c descending, rows
+ *   r < c get b[r] - rnd(L[c][r] * b[c]); then the interchanges in reverse
+ *   order (c = n-1 .. 0).
+ * Rpotrf, upper: A = U^T U with U in the upper triangle.  The upper variant
+ *   is the lower one transposed: U^T is the lower factor, by the schedule
+ *   above, of the symmetric matrix whose lower triangle is the transpose of
+ *   A's upper triangle.  The strict lower triangle of A is neither read nor
+ *   written; a failed diagonal leaves the same partial state, transposed.
+ * Rpotrs, upper: forward U^T: for c ascending, b[c] = b[c] / U[c][c], rows
+ *   r > c get b[r] - rnd(U[c][r] * b[c]); backward U: for c descending,
+ *   b[c] = b[c] / U[c][c], rows r < c get b[r] - rnd(U[r][c] * b[c]).
  */
+#include <stdlib.h>
 #include <stdint.h>
 
 #include "posit_oracle.h"
@@ -189,5 +205,52 @@ void oracle_potrs(int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint3
     for (int64_t r = 0; r < c; ++r)
       for (int64_t q = 0; q < nrhs; ++q)
         B[r * ldb + q] = pfms(B[r * ldb + q], L[c * lda + r], B[c * ldb + q]);
+  }
+}
+
+void oracle_getrs_trans(int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+                        const int32_t* ipiv, uint32_t* B, int64_t ldb) {
+  for (int64_t c = 0; c < n; ++c) {
+    for (int64_t q = 0; q < nrhs; ++q) B[c * ldb + q] = pdiv(B[c * ldb + q], LU[c * lda + c]);
+    for (int64_t r = c + 1; r < n; ++r)
+      for (int64_t q = 0; q < nrhs; ++q)
+        B[r * ldb + q] = pfms(B[r * ldb + q], LU[c * lda + r], B[c * ldb + q]);
+  }
+  for (int64_t c = n - 1; c >= 0; --c)
+    for (int64_t r = 0; r < c; ++r)
+      for (int64_t q = 0; q < nrhs; ++q)
+        B[r * ldb + q] = pfms(B[r * ldb + q], LU[c * lda + r], B[c * ldb + q]);
+  for (int64_t c = n - 1; c >= 0; --c)
+    if (ipiv[c] != c) swap_rows(B, ldb, c, ipiv[c], 0, nrhs);
+}
+
+/* returns 0, or -1 when the transposed copy cannot be allocated */
+int oracle_potrf_upper(int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
+  *info = 0;
+  if (n == 0) return 0;
+  uint32_t* T = (uint32_t*)malloc((size_t)n * (size_t)n * sizeof(uint32_t));
+  if (T == NULL) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) T[i * n + j] = j <= i ? A[j * lda + i] : 0u;
+  oracle_potrf(n, nb, T, n, info);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) A[j * lda + i] = T[i * n + j];
+  free(T);
+  return 0;
+}
+
+void oracle_potrs_upper(int64_t n, int64_t nrhs, const uint32_t* U, int64_t lda, uint32_t* B,
+                        int64_t ldb) {
+  for (int64_t c = 0; c < n; ++c) {
+    for (int64_t q = 0; q < nrhs; ++q) B[c * ldb + q] = pdiv(B[c * ldb + q], U[c * lda + c]);
+    for (int64_t r = c + 1; r < n; ++r)
+      for (int64_t q = 0; q < nrhs; ++q)
+        B[r * ldb + q] = pfms(B[r * ldb + q], U[c * lda + r], B[c * ldb + q]);
+  }
+  for (int64_t c = n - 1; c >= 0; --c) {
+    for (int64_t q = 0; q < nrhs; ++q) B[c * ldb + q] = pdiv(B[c * ldb + q], U[c * lda + c]);
+    for (int64_t r = 0; r < c; ++r)
+      for (int64_t q = 0; q < nrhs; ++q)
+        B[r * ldb + q] = pfms(B[r * ldb + q], U[r * lda + c], B[c * ldb + q]);
   }
 }

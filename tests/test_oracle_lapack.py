@@ -59,6 +59,61 @@ def test_getrf_exact_recovery(n, nb):
     assert np.array_equal(d64(X), x)
 
 
+@pytest.mark.parametrize("n,nb", [(8, 4), (37, 16), (70, 32)])
+def test_getrs_trans_exact_recovery(n, nb):
+    """A^T x = b with P A = L U from exact factors and shuffled rows: every
+    intermediate (U^-T b = L^T P x, then P x) is a short dyadic number, so the
+    integer x comes back exactly, with the interchanges undone in reverse."""
+    rng = np.random.default_rng(300 + n)
+    L, U = _exact_lu(n, rng)
+    perm = rng.permutation(n)
+    A = (L @ U)[perm]
+    LU, ipiv, info = O.getrf(p32(A), nb)
+    assert info == 0
+    assert not np.array_equal(ipiv, np.arange(n))
+    x = rng.integers(-5, 6, (n, 3)).astype(float)
+    X = O.getrs(LU, ipiv, p32(A.T @ x), trans=True)
+    assert np.array_equal(d64(X), x)
+    # the untransposed solve of the same factors is a different system
+    X2 = O.getrs(LU, ipiv, p32(A @ x))
+    assert np.array_equal(d64(X2), x)
+
+
+@pytest.mark.parametrize("n,nb", [(9, 4), (40, 16), (100, 32)])
+def test_potrf_upper_exact_recovery(n, nb):
+    """A = U^T U with U upper, positive integer diagonal in {1, 2, 4}: the
+    factor comes back exactly in the upper triangle; the strict lower triangle
+    (filled with NaR, which would poison any use) is neither read nor written."""
+    rng = np.random.default_rng(200 + n)
+    U = np.triu(rng.integers(-2, 3, (n, n)).astype(float), 1) + np.diag(rng.choice([1.0, 2.0, 4.0], n))
+    A = U.T @ U
+    Ap = p32(A)
+    Ap[np.tril_indices(n, -1)] = NAR
+    Uf, info = O.potrf(Ap, nb, upper=True)
+    assert info == 0
+    assert np.array_equal(np.triu(d64(Uf)), U)
+    assert np.all(Uf[np.tril_indices(n, -1)] == NAR)
+    x = rng.integers(-5, 6, (n, 2)).astype(float)
+    X = O.potrs(Uf, p32(A @ x), upper=True)
+    assert np.array_equal(d64(X), x)
+
+
+def test_potrf_upper_residual_and_info():
+    case = W.chol_case(150)
+    A = p32(case.A)
+    Uf, info = O.potrf(A, 64, upper=True)
+    assert info == 0
+    U = np.triu(d64(Uf))
+    Ad = d64(A)
+    res = np.linalg.norm(np.triu(Ad - U.T @ U)) / np.linalg.norm(Ad)
+    assert res < 200 * 2.0 ** -27
+    S = np.eye(10) * 2.0
+    S[6, 6] = -1.0
+    Sf, info = O.potrf(p32(S), 4, upper=True)
+    assert info == 7
+    assert np.array_equal(d64(Sf)[7:, 7:], S[7:, 7:])   # untouched after the stop
+
+
 @pytest.mark.parametrize("n,nb", [(9, 4), (40, 16), (100, 32)])
 def test_potrf_exact_recovery(n, nb):
     """A = L L^T with L lower, positive integer diagonal in {1, 2, 4} and small

@@ -18,6 +18,13 @@ algorithm) and in a different loop organisation where the reading allows one:
 * the trailing updates through the checker's own Rgemm element (dot product
   from zero in ascending k, then alpha = -1 and beta = 1).
 
+The transposed solve (A^T X = B from P A = L U) and the upper Cholesky
+forms (A = U^T U) are evaluated the same way: the transposed solve element by
+element with the interchanges applied as one permutation, the upper
+factorisation in LAPACK's upper loop organisation (rows of U, not the
+transposed lower factor the oracle takes), with the strict lower triangle
+filled with patterns that must be neither read nor changed.
+
 Factors, pivots, info and solutions must agree bit for bit.  Planted mistakes
 in a copy of ``ref_lapack.c`` (an unblocked trailing update, a reciprocal in
 place of the division, U12 in descending order, a missing division in
@@ -177,6 +184,90 @@ def sched_potrs(L, B0):
     return Xs
 
 
+def _perm_from_ipiv(ipiv):
+    """Row i of P A is row perm[i] of A (the interchanges applied in order)."""
+    perm = list(range(len(ipiv)))
+    for c, p in enumerate(ipiv):
+        perm[c], perm[p] = perm[p], perm[c]
+    return perm
+
+
+def sched_getrs_trans(LU, ipiv, B0):
+    """A^T X = B with P A = L U: U^T Y = B, L^T Z = Y, X = P^T Z."""
+    n, nrhs = len(B0), len(B0[0]) if len(B0) else 0
+    Y = [[0] * nrhs for _ in range(n)]
+    for r in range(n):
+        for q in range(nrhs):
+            x = int(B0[r][q])
+            for c in range(r):
+                x = _fms(x, LU[c][r], Y[c][q])
+            Y[r][q] = X.div(N, x, LU[r][r])
+    Z = [[0] * nrhs for _ in range(n)]
+    for r in range(n - 1, -1, -1):
+        for q in range(nrhs):
+            x = Y[r][q]
+            for c in range(n - 1, r, -1):
+                x = _fms(x, LU[c][r], Z[c][q])
+            Z[r][q] = x
+    perm = _perm_from_ipiv(ipiv)
+    Xs = [None] * n
+    for i in range(n):
+        Xs[perm[i]] = Z[i]
+    return Xs
+
+
+def sched_potrf_upper(A0, nb):
+    """A = U^T U in LAPACK's upper organisation: row c of the diagonal block
+    is divided by its root and updates the rows below it; then U12 column by
+    column and the upper triangle of the trailing matrix by Rgemm elements
+    (U12^T U12)."""
+    A = [[int(x) for x in row] for row in A0]
+    n = len(A)
+    for j in range(0, n, nb):
+        je = min(j + nb, n)
+        for c in range(j, je):
+            v = X.decode(N, A[c][c])
+            if v is None or v <= 0:
+                return A, c + 1
+            d = X.sqrt(N, A[c][c])
+            A[c][c] = d
+            for q in range(c + 1, je):
+                A[c][q] = X.div(N, A[c][q], d)
+            for i in range(c + 1, je):
+                for q in range(i, je):
+                    A[i][q] = _fms(A[i][q], A[c][i], A[c][q])
+        for r in range(je, n):
+            for c in range(j, je):
+                x = A[c][r]
+                for q in range(j, c):
+                    x = _fms(x, A[q][r], A[q][c])
+                A[c][r] = X.div(N, x, A[c][c])
+        for i in range(je, n):
+            for q in range(i, n):
+                A[i][q] = X.gemm_element([A[p][i] for p in range(j, je)],
+                                         [A[p][q] for p in range(j, je)], A[i][q], MINUS_ONE, ONE)
+    return A, 0
+
+
+def sched_potrs_upper(U, B0):
+    n, nrhs = len(B0), len(B0[0]) if len(B0) else 0
+    Y = [[0] * nrhs for _ in range(n)]
+    for r in range(n):
+        for q in range(nrhs):
+            x = int(B0[r][q])
+            for c in range(r):
+                x = _fms(x, U[c][r], Y[c][q])
+            Y[r][q] = X.div(N, x, U[r][r])
+    Xs = [[0] * nrhs for _ in range(n)]
+    for r in range(n - 1, -1, -1):
+        for q in range(nrhs):
+            x = Y[r][q]
+            for c in range(n - 1, r, -1):
+                x = _fms(x, U[r][c], Xs[c][q])
+            Xs[r][q] = X.div(N, x, U[r][r])
+    return Xs
+
+
 # ---- tiny cases ------------------------------------------------------------------
 
 def _enc(x):
@@ -301,6 +392,29 @@ def _chol_expected(case):
             info, None if Xs is None else np.array(Xs, np.uint32).reshape(n, nrhs))
 
 
+@functools.lru_cache(maxsize=None)
+def _lu_trans_expected(case):
+    A, B, LU, ipiv, info, _ = _lu_expected(case)
+    Xs = sched_getrs_trans(LU.tolist(), ipiv.tolist(), B.tolist())
+    return np.array(Xs, np.uint32).reshape(B.shape)
+
+
+@functools.lru_cache(maxsize=None)
+def _chol_upper_expected(case):
+    """The lower case's symmetric matrix with its strict lower triangle
+    replaced by unrelated patterns (never read by the upper form)."""
+    n, nb, kind, seed = case
+    A, B, _, _, _ = _chol_expected(case)
+    rng = np.random.default_rng(seed + 50000)
+    Au = A.copy()
+    for i in range(n):
+        for q in range(i):
+            Au[i, q] = _regime_pattern(rng)
+    U, info = sched_potrf_upper(Au.tolist(), nb)
+    Xs = sched_potrs_upper(U, B.tolist()) if info == 0 else None
+    return Au, np.array(U, np.uint32), info, None if Xs is None else np.array(Xs, np.uint32).reshape(B.shape)
+
+
 # ---- the oracle (or a planted copy of it) on the same cases ------------------------
 
 class _Lib:
@@ -312,6 +426,10 @@ class _Lib:
         L.oracle_getrs.argtypes = [i64, i64, vp, i64, vp, vp, i64]
         L.oracle_potrf.argtypes = [i64, i64, vp, i64, vp]
         L.oracle_potrs.argtypes = [i64, i64, vp, i64, vp, i64]
+        L.oracle_getrs_trans.argtypes = [i64, i64, vp, i64, vp, vp, i64]
+        L.oracle_potrf_upper.argtypes = [i64, i64, vp, i64, vp]
+        L.oracle_potrf_upper.restype = ctypes.c_int
+        L.oracle_potrs_upper.argtypes = [i64, i64, vp, i64, vp, i64]
         self.L = L
 
     def getrf(self, A, nb):
@@ -322,24 +440,29 @@ class _Lib:
         self.L.oracle_getrf(n, nb, A.ctypes.data, n, ipiv.ctypes.data, info.ctypes.data)
         return A, ipiv, int(info[0])
 
-    def getrs(self, LU, ipiv, B):
+    def getrs(self, LU, ipiv, B, trans=False):
         Bc = np.array(B, np.uint32, copy=True, order="C")
         LU = np.ascontiguousarray(LU, np.uint32)
         ipiv = np.ascontiguousarray(ipiv, np.int32)
-        self.L.oracle_getrs(LU.shape[0], Bc.shape[1], LU.ctypes.data, LU.shape[0], ipiv.ctypes.data,
-                            Bc.ctypes.data, Bc.shape[1])
+        f = self.L.oracle_getrs_trans if trans else self.L.oracle_getrs
+        f(LU.shape[0], Bc.shape[1], LU.ctypes.data, LU.shape[0], ipiv.ctypes.data, Bc.ctypes.data,
+          Bc.shape[1])
         return Bc
 
-    def potrf(self, A, nb):
+    def potrf(self, A, nb, upper=False):
         A = np.array(A, np.uint32, copy=True, order="C")
         info = np.zeros(1, np.int32)
-        self.L.oracle_potrf(A.shape[0], nb, A.ctypes.data, A.shape[0], info.ctypes.data)
+        if upper:
+            assert self.L.oracle_potrf_upper(A.shape[0], nb, A.ctypes.data, A.shape[0], info.ctypes.data) == 0
+        else:
+            self.L.oracle_potrf(A.shape[0], nb, A.ctypes.data, A.shape[0], info.ctypes.data)
         return A, int(info[0])
 
-    def potrs(self, L, B):
+    def potrs(self, L, B, upper=False):
         Bc = np.array(B, np.uint32, copy=True, order="C")
         L = np.ascontiguousarray(L, np.uint32)
-        self.L.oracle_potrs(L.shape[0], Bc.shape[1], L.ctypes.data, L.shape[0], Bc.ctypes.data, Bc.shape[1])
+        f = self.L.oracle_potrs_upper if upper else self.L.oracle_potrs
+        f(L.shape[0], Bc.shape[1], L.ctypes.data, L.shape[0], Bc.ctypes.data, Bc.shape[1])
         return Bc
 
 
@@ -354,6 +477,8 @@ def _lu_mismatch(lib, case):
         return "factors differ"
     if not np.array_equal(lib.getrs(LU, ipiv, B), Xs):
         return "solution differs"
+    if not np.array_equal(lib.getrs(LU, ipiv, B, trans=True), _lu_trans_expected(case)):
+        return "transposed solution differs"
     return None
 
 
@@ -366,6 +491,14 @@ def _chol_mismatch(lib, case):
         return "factor differs"
     if Xs is not None and not np.array_equal(lib.potrs(L, B), Xs):
         return "solution differs"
+    Au, U, uinfo, UXs = _chol_upper_expected(case)
+    gU, ginfo = lib.potrf(Au, case[1], upper=True)
+    if ginfo != uinfo:
+        return f"upper info {ginfo} != {uinfo}"
+    if not np.array_equal(gU, U):
+        return "upper factor differs"
+    if UXs is not None and not np.array_equal(lib.potrs(U, B, upper=True), UXs):
+        return "upper solution differs"
     return None
 
 
@@ -394,6 +527,8 @@ def test_cases_reach_the_rare_paths():
     chol = [_chol_expected(c)[3] for c in CHOL_CASES]
     assert sum(i > 0 for i in chol) >= 10 and sum(i == 0 for i in chol) >= 20
     assert len({i for i in chol if i > 0}) >= 4
+    # the upper form sees the same symmetric matrix: same info as the lower one
+    assert [_chol_upper_expected(c)[2] for c in CHOL_CASES] == chol
 
 
 # ---- planted mistakes in ref_lapack.c ----------------------------------------------
@@ -452,6 +587,28 @@ MUTANTS = {
       for (int64_t q = 0; q < nrhs; ++q)
         B[r * ldb + q] = pfms(B[r * ldb + q], pdiv(LU[r * lda + c], LU[c * lda + c]), B[c * ldb + q]);
     for (int64_t q = 0; q < nrhs; ++q) B[c * ldb + q] = pdiv(B[c * ldb + q], LU[c * lda + c]);"""),
+    # the transposed solve's interchanges applied in forward order
+    "getrs_trans_pivots_forward": (
+        """  for (int64_t c = n - 1; c >= 0; --c)
+    if (ipiv[c] != c) swap_rows(B, ldb, c, ipiv[c], 0, nrhs);""",
+        """  for (int64_t c = 0; c < n; ++c)
+    if (ipiv[c] != c) swap_rows(B, ldb, c, ipiv[c], 0, nrhs);"""),
+    # the transposed solve's backward step with L instead of L^T
+    "getrs_trans_untransposed_l": (
+        """        B[r * ldb + q] = pfms(B[r * ldb + q], LU[c * lda + r], B[c * ldb + q]);
+  for (int64_t c = n - 1; c >= 0; --c)
+    if (ipiv[c] != c)""",
+        """        B[r * ldb + q] = pfms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
+  for (int64_t c = n - 1; c >= 0; --c)
+    if (ipiv[c] != c)"""),
+    # the upper Cholesky reading the lower triangle
+    "potrf_upper_reads_lower": (
+        "T[i * n + j] = j <= i ? A[j * lda + i] : 0u;",
+        "T[i * n + j] = j <= i ? A[i * lda + j] : 0u;"),
+    # the upper solve's backward step with U^T instead of U
+    "potrs_upper_backward_transposed": (
+        "B[r * ldb + q] = pfms(B[r * ldb + q], U[r * lda + c], B[c * ldb + q]);",
+        "B[r * ldb + q] = pfms(B[r * ldb + q], U[c * lda + r], B[c * ldb + q]);"),
     # a zero pivot stops the panel's updates too
     "zero_pivot_skips_update": (
         """        if (*info == 0) *info = (int32_t)(c + 1);

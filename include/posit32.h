@@ -41,6 +41,7 @@ extern "C" {
 typedef uint32_t posit32_t;
 
 enum { P32_NOTRANS = 0, P32_TRANS = 1 };
+enum { P32_LOWER = 0, P32_UPPER = 1 };
 
 #define P32_OK 0
 #define P32_E_HIP (-1000)           /* P32_E_HIP - hipError_t */
@@ -125,23 +126,38 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  *   ipiv: device int32[n], 0-based (row c was swapped with row ipiv[c]).
  *   info: device int32[1], 0 or the 1-based column of the first zero pivot
  *   (-1: see below).
- * posit32_getrs -- solve A X = B with the output of posit32_getrf; B is n x
- *   nrhs (ldb >= nrhs), overwritten by X.  Interchanges in order; forward
- *   L (unit): for c ascending, rows r > c get B[r] - rnd(L[r][c]*B[c]);
- *   backward U: for c descending, B[c] = B[c] / U[c][c], then rows r < c get
+ * posit32_getrs -- solve op(A) X = B with the output of posit32_getrf; B is
+ *   n x nrhs (ldb >= nrhs), overwritten by X.
+ *   op = P32_NOTRANS (A X = B): interchanges in order; forward L (unit): for
+ *   c ascending, rows r > c get B[r] - rnd(L[r][c]*B[c]); backward U: for c
+ *   descending, B[c] = B[c] / U[c][c], then rows r < c get
  *   B[r] - rnd(U[r][c]*B[c]).
- * posit32_potrf -- A = L L^T (lower), in place in the lower triangle; the
- *   strict upper triangle is neither read nor written.  Per diagonal block:
+ *   op = P32_TRANS (A^T X = B, LAPACK's trans = 'T'; P A = L U gives
+ *   A^T = U^T L^T P): forward U^T: for c ascending, B[c] = B[c] / U[c][c],
+ *   rows r > c get B[r] - rnd(U[c][r]*B[c]); backward L^T (unit): for c
+ *   descending, rows r < c get B[r] - rnd(L[c][r]*B[c]); then the
+ *   interchanges undone in reverse order (c = n-1 .. 0).
+ * posit32_potrf -- uplo = P32_LOWER: A = L L^T, in place in the lower
+ *   triangle; the strict upper triangle is neither read nor written.
+ *   uplo = P32_UPPER: A = U^T U, in place in the upper triangle, the strict
+ *   lower triangle neither used nor changed; U is the transpose of the lower
+ *   factor of the symmetric matrix held by the upper triangle, bit for bit
+ *   (LAPACK's upper variant is the lower one transposed).  The library
+ *   exchanges the two strict triangles in place before and after the lower
+ *   factorisation (n <= 2^20), so they hold each other's values while the
+ *   call runs.  Lower form, per diagonal block:
  *   for each column c: if A[c][c] <= 0 or NaR, info = c+1 and the call stops
  *   (later blocks are not touched); A[c][c] = sqrt(A[c][c]); the block's
  *   rows below are divided by it; the block's lower triangle gets
  *   A[i][q] - rnd(A[i][c]*A[q][c]).  Then L21 = A21 L11^-T row by row
  *   (ascending columns, division by L[c][c]), and the lower triangle of
  *   A22 = Rgemm(-1, 1, L21, L21^T).
- * posit32_potrs -- solve A X = B with the output of posit32_potrf: forward L
- *   (for c ascending: B[c] = B[c] / L[c][c], rows below get
- *   B[r] - rnd(L[r][c]*B[c])), then backward L^T (for c descending:
- *   B[c] = B[c] / L[c][c], rows above get B[r] - rnd(L[c][r]*B[c])).
+ * posit32_potrs -- solve A X = B with the output of posit32_potrf (same
+ *   uplo).  Lower: forward L (for c ascending: B[c] = B[c] / L[c][c], rows
+ *   below get B[r] - rnd(L[r][c]*B[c])), then backward L^T (for c
+ *   descending: B[c] = B[c] / L[c][c], rows above get
+ *   B[r] - rnd(L[c][r]*B[c])).  Upper: the same with L[r][c] = U[c][r]
+ *   (forward U^T, backward U).
  *
  * All pointers are device memory; calls are stream-ordered and asynchronous
  * (info is written on the device).  posit32_getrf factors each panel in one
@@ -151,19 +167,28 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  * of the input), info is set to -1.  posit32_potrf takes a stream-ordered
  * temporary of 1 KiB per row (the block column it restores after a failed
  * diagonal).
- * Errors: -2 n < 0 (getrf: also n > 2^24 - 2, pivot rows are carried in 24
- * bits); -3 nb outside [1, 256] (getrf/potrf) or nrhs outside [0, 2^31 - 1]
- * (getrs/potrs); -4/-5 null matrix or lda < max(1, n); then the remaining
- * pointer/leading-dimension arguments in order (-6, -7, ...).
+ * Errors (a negative value is minus the 1-based position of the first bad
+ * argument, counting the stream as 1): a bad op / uplo flag; n < 0 (getrf:
+ * also n > 2^24 - 2, pivot rows are carried in 24 bits; upper potrf: also
+ * n > 2^20); nb outside [1, 256] (getrf/potrf) or nrhs outside
+ * [0, 2^31 - 1] (getrs/potrs); a null matrix or lda < max(1, n); then the
+ * remaining pointer/leading-dimension arguments in order.
+ *
+ * Graph capture: posit32_getrs and posit32_potrs launch ordinary kernels
+ * only and allocate nothing, so a caller may capture them in a hipGraph
+ * (hipStreamBeginCapture on its stream) and replay them, like
+ * posit32_gemm, posit32_elementwise, the conversions and the batched calls
+ * below.  posit32_getrf (cooperative launches, a stream-ordered temporary)
+ * and posit32_potrf (a stream-ordered temporary) are not capturable.
  */
 int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                   int32_t* ipiv, int32_t* info);
-int posit32_getrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
-                  const int32_t* ipiv, posit32_t* B, int64_t ldb);
-int posit32_potrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+int posit32_getrs(void* stream, int op, int64_t n, int64_t nrhs, const posit32_t* LU,
+                  int64_t lda, const int32_t* ipiv, posit32_t* B, int64_t ldb);
+int posit32_potrf(void* stream, int uplo, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                   int32_t* info);
-int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
-                  posit32_t* B, int64_t ldb);
+int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32_t* L,
+                  int64_t lda, posit32_t* B, int64_t ldb);
 
 /*
  * Variable-size batches of the factorisations and solves above: count

@@ -8,7 +8,7 @@
 
 extern "C" {
 
-int posit32_version(void) { return 110; }
+int posit32_version(void) { return 200; }
 
 const char* posit32_strerror(int code) {
   if (code == 0) return "ok";
@@ -77,36 +77,41 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
   return p32::launch_getrf((hipStream_t)stream, n, nb, A, lda, ipiv, info);
 }
 
-int posit32_getrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
+int posit32_getrs(void* stream, int op, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
                   const int32_t* ipiv, posit32_t* B, int64_t ldb) {
-  if (n < 0) return -2;
-  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -3;   // one workgroup per right-hand side
-  if (n > 0 && LU == nullptr) return -4;
-  if (lda < (n > 1 ? n : 1)) return -5;
-  if (n > 0 && ipiv == nullptr) return -6;
+  if (op != P32_NOTRANS && op != P32_TRANS) return -2;
+  if (n < 0) return -3;
+  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -4;   // one workgroup per right-hand side
+  if (n > 0 && LU == nullptr) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && ipiv == nullptr) return -7;
+  if (n > 0 && nrhs > 0 && B == nullptr) return -8;
+  if (ldb < (nrhs > 1 ? nrhs : 1)) return -9;
+  return p32::launch_getrs((hipStream_t)stream, op, n, nrhs, LU, lda, ipiv, B, ldb);
+}
+
+int posit32_potrf(void* stream, int uplo, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                  int32_t* info) {
+  if (uplo != P32_LOWER && uplo != P32_UPPER) return -2;
+  if (n < 0) return -3;
+  if (nb < 1 || nb > 256) return -4;
+  if (n > 0 && A == nullptr) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (info == nullptr) return -7;
+  if (uplo == P32_UPPER && n > ((int64_t)1 << 20)) return -3;   // triangle exchange: one launch
+  return p32::launch_potrf((hipStream_t)stream, uplo, n, nb, A, lda, info);
+}
+
+int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
+                  posit32_t* B, int64_t ldb) {
+  if (uplo != P32_LOWER && uplo != P32_UPPER) return -2;
+  if (n < 0) return -3;
+  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -4;
+  if (n > 0 && L == nullptr) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
   if (n > 0 && nrhs > 0 && B == nullptr) return -7;
   if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
-  return p32::launch_getrs((hipStream_t)stream, n, nrhs, LU, lda, ipiv, B, ldb);
-}
-
-int posit32_potrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda, int32_t* info) {
-  if (n < 0) return -2;
-  if (nb < 1 || nb > 256) return -3;
-  if (n > 0 && A == nullptr) return -4;
-  if (lda < (n > 1 ? n : 1)) return -5;
-  if (info == nullptr) return -6;
-  return p32::launch_potrf((hipStream_t)stream, n, nb, A, lda, info);
-}
-
-int posit32_potrs(void* stream, int64_t n, int64_t nrhs, const posit32_t* L, int64_t lda,
-                  posit32_t* B, int64_t ldb) {
-  if (n < 0) return -2;
-  if (nrhs < 0 || nrhs > 0x7FFFFFFF) return -3;
-  if (n > 0 && L == nullptr) return -4;
-  if (lda < (n > 1 ? n : 1)) return -5;
-  if (n > 0 && nrhs > 0 && B == nullptr) return -6;
-  if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
-  return p32::launch_potrs((hipStream_t)stream, n, nrhs, L, lda, B, ldb);
+  return p32::launch_potrs((hipStream_t)stream, uplo, n, nrhs, L, lda, B, ldb);
 }
 
 // ---- variable-size batches ---------------------------------------------------

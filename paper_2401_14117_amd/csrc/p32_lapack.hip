@@ -551,13 +551,20 @@ trsm_chol_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t r_begin, int64_t
 }
 
 // ---- triangular solves -----------------------------------------------------
-// kind 0: L unit lower, forward (getrs);  kind 1: U upper, backward (getrs)
+// kind 0: L unit lower, forward (getrs);  kind 1: U upper, backward (getrs,
+//         and the upper potrs's U)
 // kind 2: L lower, forward (potrs);       kind 3: L^T, backward (potrs)
-// T(r, c) is the coefficient of x[c] in row r of the triangular system.
+// kind 4: U^T, forward (the transposed getrs, and the upper potrs's U^T)
+// kind 5: L^T unit, backward (the transposed getrs)
+// T(r, c) is the coefficient of x[c] in row r of the triangular system; the
+// transposed kinds (3..5) read it from row c of the stored factor.
+__host__ __device__ constexpr bool kind_forward(int kind) { return kind == 0 || kind == 2 || kind == 4; }
+__host__ __device__ constexpr bool kind_unit(int kind) { return kind == 0 || kind == 5; }
+__host__ __device__ constexpr bool kind_trans(int kind) { return kind >= 3; }
 
 __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int kind, int64_t r,
                                              int64_t c) {
-  return kind == 3 ? M[c * lda + r] : M[r * lda + c];
+  return kind_trans(kind) ? M[c * lda + r] : M[r * lda + c];
 }
 
 // Diagonal block [s, s+bs) (bs <= kTrsvBlock = 64) of the solve for one
@@ -578,17 +585,18 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
                  int64_t nrhs, int64_t s, int bs) {
   __shared__ int2 coef[kTrsvBlock][kTrsvBlock + 1];
   __shared__ lut_t lut[256];
-  constexpr bool forward = kind == 0 || kind == 2;
-  constexpr bool unit = kind == 0;
+  constexpr bool forward = kind_forward(kind);
+  constexpr bool unit = kind_unit(kind);
   const int lane = threadIdx.x;
   const int64_t q = blockIdx.x;
   // coef[r][u]: coefficient of the u-th column in solve order in row r,
   // decoded; only the entries strictly below the diagonal in solve order are
   // loaded.  The lane index is u (kinds 0..2: a row of M is contiguous) or r
-  // (kind 3: a column of M is), and all of a lane's loads are issued before
-  // the first is decoded, so the staging waits on memory once, not per row.
+  // (kinds 3..5: a column of M is), and all of a lane's loads are issued
+  // before the first is decoded, so the staging waits on memory once, not per
+  // row.
   {
-    constexpr bool trans = kind == 3;
+    constexpr bool trans = kind_trans(kind);
     uint32_t mv[kTrsvBlock];
 #pragma unroll
     for (int a = 0; a < kTrsvBlock; ++a) {
@@ -668,7 +676,7 @@ trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __rest
   __shared__ lut_t lut[256];
   for (int i = threadIdx.x; i < 256; i += kTrsvBlock) lut[i] = make_lut_entry(i);
   __syncthreads();
-  const bool forward = kind == 0 || kind == 2;
+  const bool forward = kind_forward(kind);
   const int lane = threadIdx.x;
   const int64_t r = r0 + (int64_t)blockIdx.x * kTrsvBlock + lane;
   const bool mine = r < r1;
@@ -715,12 +723,14 @@ trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __rest
   }
 }
 
-// row interchanges of getrs, in order, one thread per right-hand side
+// row interchanges of getrs, in order (reverse: in reverse order, which
+// undoes them), one thread per right-hand side
 __global__ void apply_pivots_kernel(uint32_t* __restrict__ B, int64_t ldb, int64_t n, int64_t nrhs,
-                                    const int32_t* __restrict__ ipiv) {
+                                    const int32_t* __restrict__ ipiv, int reverse) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nrhs) return;
-  for (int64_t c = 0; c < n; ++c) {
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t c = reverse ? n - 1 - t : t;
     const int64_t p = ipiv[c];
     if (p != c) {
       const uint32_t x = B[c * ldb + q];
@@ -735,7 +745,7 @@ __global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
 static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32_t* B, int64_t ldb,
                 int64_t nrhs, int kind) {
   const int64_t bsz = kTrsvBlock;
-  const bool forward = kind == 0 || kind == 2;
+  const bool forward = kind_forward(kind);
   const int64_t nblk = (n + bsz - 1) / bsz;
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t s0 = forward ? b * bsz : (nblk - 1 - b) * bsz;
@@ -744,7 +754,9 @@ static int trsv(hipStream_t s, const uint32_t* M, int64_t lda, int64_t n, uint32
     if (kind == 0) hipLaunchKernelGGL(trsv_diag_kernel<0>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
     else if (kind == 1) hipLaunchKernelGGL(trsv_diag_kernel<1>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
     else if (kind == 2) hipLaunchKernelGGL(trsv_diag_kernel<2>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
-    else hipLaunchKernelGGL(trsv_diag_kernel<3>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else if (kind == 3) hipLaunchKernelGGL(trsv_diag_kernel<3>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else if (kind == 4) hipLaunchKernelGGL(trsv_diag_kernel<4>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
+    else hipLaunchKernelGGL(trsv_diag_kernel<5>, grid, block, 0, s, M, lda, B, ldb, nrhs, s0, (int)bs);
     const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? n : s0;
     if (r1 > r0) {
       const unsigned gy = (unsigned)(nrhs < 65535 ? nrhs : 65535);
@@ -839,11 +851,21 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
   return launch_status();
 }
 
-int launch_getrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+// trans == 0: A X = B, i.e. interchanges, L, U.  trans == 1: A^T X = B with
+// A^T = U^T L^T P: U^T forward, L^T (unit) backward, then the interchanges
+// undone in reverse order.
+int launch_getrs(hipStream_t s, int trans, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
                  const int32_t* ipiv, uint32_t* B, int64_t ldb) {
   if (n == 0 || nrhs == 0) return 0;
-  hipLaunchKernelGGL(apply_pivots_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, B, ldb, n,
-                     nrhs, ipiv);
+  const dim3 pgrid((unsigned)((nrhs + 63) / 64)), pblock(64);
+  if (trans) {
+    int rc = trsv(s, LU, lda, n, B, ldb, nrhs, 4);
+    if (rc == 0) rc = trsv(s, LU, lda, n, B, ldb, nrhs, 5);
+    if (rc != 0) return rc;
+    hipLaunchKernelGGL(apply_pivots_kernel, pgrid, pblock, 0, s, B, ldb, n, nrhs, ipiv, 1);
+    return launch_status();
+  }
+  hipLaunchKernelGGL(apply_pivots_kernel, pgrid, pblock, 0, s, B, ldb, n, nrhs, ipiv, 0);
   int rc = trsv(s, LU, lda, n, B, ldb, nrhs, 0);
   if (rc != 0) return rc;
   return trsv(s, LU, lda, n, B, ldb, nrhs, 1);
@@ -882,7 +904,23 @@ static_assert(kCholSub <= kCholTrsmMax, "trsm_chol_kernel stages at most kCholTr
 // column are restored from a copy taken before the block started and the
 // block is refactored unblocked, which stops at the same column with the
 // state the unblocked order leaves.
-int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
+static int potrf_lower(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info);
+
+// upper == 1: A = U^T U with U in the upper triangle, U = L^T for the lower
+// factor L of the symmetric matrix held by A's upper triangle.  The two
+// strict triangles are exchanged, the lower form runs (it neither reads nor
+// writes the strict upper triangle, which now holds the caller's lower
+// triangle), and the triangles are exchanged back: U lands in the upper
+// triangle and the strict lower triangle is restored unchanged.
+int launch_potrf(hipStream_t s, int upper, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
+  if (!upper) return potrf_lower(s, n, nb, A, lda, info);
+  int rc = launch_swap_triangles(s, A, lda, n);
+  const int rc2 = rc == 0 ? potrf_lower(s, n, nb, A, lda, info) : 0;
+  if (rc == 0) rc = launch_swap_triangles(s, A, lda, n);   // also after a failed launch: restore the layout
+  return rc2 != 0 ? rc2 : rc;
+}
+
+static int potrf_lower(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
   if (n == 0) return launch_status();
   uint32_t* saved = nullptr;
@@ -925,12 +963,60 @@ int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
   return launch_status();
 }
 
-int launch_potrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint32_t* B,
-                 int64_t ldb) {
+// upper == 0: A = L L^T (L forward, L^T backward).  upper == 1: A = U^T U
+// with U = L^T: the same two solves reading the factor transposed (U^T
+// forward, U backward), so the bits are those of the lower form on the
+// transposed factor.
+int launch_potrs(hipStream_t s, int upper, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda,
+                 uint32_t* B, int64_t ldb) {
   if (n == 0 || nrhs == 0) return 0;
-  int rc = trsv(s, L, lda, n, B, ldb, nrhs, 2);
+  int rc = trsv(s, L, lda, n, B, ldb, nrhs, upper ? 4 : 2);
   if (rc != 0) return rc;
-  return trsv(s, L, lda, n, B, ldb, nrhs, 3);
+  return trsv(s, L, lda, n, B, ldb, nrhs, upper ? 1 : 3);
+}
+
+// Exchanges the strict lower and strict upper triangles of the n x n matrix
+// A (A[i][j] <-> A[j][i] for i != j), in place.  One workgroup per pair of
+// 32 x 32 tiles (bi, bj) with bi >= bj: both tiles are read into LDS with
+// coalesced loads and written back transposed into each other's place; a
+// diagonal tile is transposed in place.  The diagonal is rewritten with its
+// own values.
+constexpr int kSwapTile = 32;
+
+__global__ void __launch_bounds__(256)
+swap_triangles_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n) {
+  __shared__ uint32_t ta[kSwapTile][kSwapTile + 1], tb[kSwapTile][kSwapTile + 1];
+  // tile pair t -> (bi, bj) with bi >= bj: t = bi (bi + 1) / 2 + bj
+  const int64_t t = blockIdx.x;
+  int64_t bi = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+  while (bi * (bi + 1) / 2 > t) --bi;
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  const int64_t bj = t - bi * (bi + 1) / 2;
+  const int64_t i0 = bi * kSwapTile, j0 = bj * kSwapTile;
+  const int tx = threadIdx.x % kSwapTile, ty = threadIdx.x / kSwapTile;   // 32 x 8
+  for (int r = ty; r < kSwapTile; r += 8) {
+    const int64_t gi = i0 + r, gj = j0 + tx;          // tile (bi, bj), row r
+    if (gi < n && gj < n) ta[r][tx] = A[gi * lda + gj];
+    const int64_t hi = j0 + r, hj = i0 + tx;          // tile (bj, bi), row r
+    if (bi != bj && hi < n && hj < n) tb[r][tx] = A[hi * lda + hj];
+  }
+  __syncthreads();
+  for (int r = ty; r < kSwapTile; r += 8) {
+    // (bi, bj) receives the transpose of (bj, bi); a diagonal tile its own
+    const int64_t gi = i0 + r, gj = j0 + tx;
+    if (gi < n && gj < n) A[gi * lda + gj] = bi != bj ? tb[tx][r] : ta[tx][r];
+    const int64_t hi = j0 + r, hj = i0 + tx;
+    if (bi != bj && hi < n && hj < n) A[hi * lda + hj] = ta[tx][r];
+  }
+}
+
+int launch_swap_triangles(hipStream_t s, uint32_t* A, int64_t lda, int64_t n) {
+  if (n <= 1) return 0;
+  const int64_t nt = (n + kSwapTile - 1) / kSwapTile;
+  if (nt * (nt + 1) / 2 > 0x7FFFFFFF) return -1000 - (int)hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(swap_triangles_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, A, lda,
+                     n);
+  return launch_status();
 }
 
 }  // namespace p32

@@ -32,11 +32,14 @@ int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, cons
 
 int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                  int32_t* info);
-int launch_getrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
+// trans: solve A^T X = B;  upper: A = U^T U with U in the upper triangle
+int launch_getrs(hipStream_t s, int trans, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
                  const int32_t* ipiv, uint32_t* B, int64_t ldb);
-int launch_potrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info);
-int launch_potrs(hipStream_t s, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda, uint32_t* B,
-                 int64_t ldb);
+int launch_potrf(hipStream_t s, int upper, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* info);
+int launch_potrs(hipStream_t s, int upper, int64_t n, int64_t nrhs, const uint32_t* L, int64_t lda,
+                 uint32_t* B, int64_t ldb);
+// A[i][j] <-> A[j][i] for every i != j of the n x n matrix A
+int launch_swap_triangles(hipStream_t s, uint32_t* A, int64_t lda, int64_t n);
 
 // Sub-panel width per size bucket of the batched kernels: a system of order
 // n uses sub[b] for the first bucket b with n <= max_n[b] (else the last).

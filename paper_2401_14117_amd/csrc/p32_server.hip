@@ -371,10 +371,10 @@ int start_batch(posit32_queue* q, Slot& s) {
     r->info = sub++;
     if (r->kind == 0) {
       if (!r->factor_in) rc = p32::launch_getrf(q->compute, r->n, q->cfg.nb, A, r->n, ipiv, info);
-      if (!rc) rc = p32::launch_getrs(q->compute, r->n, r->nrhs, A, r->n, ipiv, B, r->nrhs);
+      if (!rc) rc = p32::launch_getrs(q->compute, 0, r->n, r->nrhs, A, r->n, ipiv, B, r->nrhs);
     } else {
-      if (!r->factor_in) rc = p32::launch_potrf(q->compute, r->n, q->cfg.nb, A, r->n, info);
-      if (!rc) rc = p32::launch_potrs(q->compute, r->n, r->nrhs, A, r->n, B, r->nrhs);
+      if (!r->factor_in) rc = p32::launch_potrf(q->compute, 0, r->n, q->cfg.nb, A, r->n, info);
+      if (!rc) rc = p32::launch_potrs(q->compute, 0, r->n, r->nrhs, A, r->n, B, r->nrhs);
     }
   }
   if (rc) return rc;

@@ -111,9 +111,9 @@ def lib() -> ctypes.CDLL:
     L.posit32_to_f64.argtypes = [vp, i64, vp, vp]
     L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
     L.posit32_getrf.argtypes = [vp, i64, i64, vp, i64, vp, vp]
-    L.posit32_getrs.argtypes = [vp, i64, i64, vp, i64, vp, vp, i64]
-    L.posit32_potrf.argtypes = [vp, i64, i64, vp, i64, vp]
-    L.posit32_potrs.argtypes = [vp, i64, i64, vp, i64, vp, i64]
+    L.posit32_getrs.argtypes = [vp, i32, i64, i64, vp, i64, vp, vp, i64]
+    L.posit32_potrf.argtypes = [vp, i32, i64, i64, vp, i64, vp]
+    L.posit32_potrs.argtypes = [vp, i32, i64, i64, vp, i64, vp, i64]
     L.posit32_getrf_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
     L.posit32_getrs_vbatched.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.posit32_gesv_vbatched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -324,28 +324,33 @@ def getrf(A: torch.Tensor, nb: int = 256, stream=None):
     return A, ipiv[:n], info
 
 
-def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
-    """In place solve with the output of getrf; B is n x nrhs (or length n)."""
+def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, stream=None,
+          trans: bool = False) -> torch.Tensor:
+    """In place solve of A X = B (trans: A^T X = B) with the output of getrf;
+    B is n x nrhs (or length n)."""
     n = _square(LU)
     B2 = _rhs(B, n)
-    _check(lib().posit32_getrs(_stream(stream), n, B2.shape[1], _ptr(LU), _ld(LU), _ptr(ipiv),
-                               _ptr(B2), _ld(B2)), "posit32_getrs")
+    _check(lib().posit32_getrs(_stream(stream), int(bool(trans)), n, B2.shape[1], _ptr(LU), _ld(LU),
+                               _ptr(ipiv), _ptr(B2), _ld(B2)), "posit32_getrs")
     return B
 
 
-def potrf(A: torch.Tensor, nb: int = 256, stream=None):
-    """In place lower Cholesky; returns (A, info)."""
+def potrf(A: torch.Tensor, nb: int = 256, stream=None, upper: bool = False):
+    """In place Cholesky, lower (A = L L^T) or upper (A = U^T U); returns
+    (A, info)."""
     n = _square(A)
     info = torch.empty(1, dtype=torch.int32, device=A.device)
-    _check(lib().posit32_potrf(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(info)), "posit32_potrf")
+    _check(lib().posit32_potrf(_stream(stream), int(bool(upper)), n, nb, _ptr(A), _ld(A), _ptr(info)),
+           "posit32_potrf")
     return A, info
 
 
-def potrs(L: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+def potrs(L: torch.Tensor, B: torch.Tensor, stream=None, upper: bool = False) -> torch.Tensor:
+    """In place solve with the output of potrf (the same upper flag)."""
     n = _square(L)
     B2 = _rhs(B, n)
-    _check(lib().posit32_potrs(_stream(stream), n, B2.shape[1], _ptr(L), _ld(L), _ptr(B2), _ld(B2)),
-           "posit32_potrs")
+    _check(lib().posit32_potrs(_stream(stream), int(bool(upper)), n, B2.shape[1], _ptr(L), _ld(L),
+                               _ptr(B2), _ld(B2)), "posit32_potrs")
     return B
 
 

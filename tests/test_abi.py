@@ -82,10 +82,34 @@ def test_factorisation_argument_errors(L):
     assert L.posit32_getrf(None, 4, 64, 8, 3, 8, 8) == -5
     assert L.posit32_getrf(None, 4, 64, 8, 4, None, 8) == -6
     assert L.posit32_getrf(None, 4, 64, 8, 4, 8, None) == -7
-    assert L.posit32_getrs(None, 4, -1, 8, 4, 8, 8, 1) == -3
-    assert L.posit32_getrs(None, 4, 2, 8, 4, 8, 8, 1) == -8
-    assert L.posit32_potrf(None, 4, 64, 8, 4, None) == -6
-    assert L.posit32_potrs(None, 4, 2, 8, 4, None, 2) == -6
+    # getrs(stream, op, n, nrhs, LU, lda, ipiv, B, ldb)
+    assert L.posit32_getrs(None, 2, 4, 1, 8, 4, 8, 8, 1) == -2
+    assert L.posit32_getrs(None, -1, 4, 1, 8, 4, 8, 8, 1) == -2
+    assert L.posit32_getrs(None, 1, -1, 1, 8, 4, 8, 8, 1) == -3
+    assert L.posit32_getrs(None, 0, 4, -1, 8, 4, 8, 8, 1) == -4
+    assert L.posit32_getrs(None, 1, 4, 1, None, 4, 8, 8, 1) == -5
+    assert L.posit32_getrs(None, 1, 4, 1, 8, 3, 8, 8, 1) == -6
+    assert L.posit32_getrs(None, 1, 4, 1, 8, 4, None, 8, 1) == -7
+    assert L.posit32_getrs(None, 1, 4, 1, 8, 4, 8, None, 1) == -8
+    assert L.posit32_getrs(None, 0, 4, 2, 8, 4, 8, 8, 1) == -9
+    assert L.posit32_getrs(None, 1, 0, 0, None, 1, None, None, 1) == 0
+    # potrf(stream, uplo, n, nb, A, lda, info)
+    assert L.posit32_potrf(None, 2, 4, 64, 8, 4, 8) == -2
+    assert L.posit32_potrf(None, 1, -4, 64, 8, 4, 8) == -3
+    assert L.posit32_potrf(None, 1, (1 << 20) + 1, 64, 8, (1 << 20) + 1, 8) == -3
+    assert L.posit32_potrf(None, 0, 4, 0, 8, 4, 8) == -4
+    assert L.posit32_potrf(None, 1, 4, 64, None, 4, 8) == -5
+    assert L.posit32_potrf(None, 1, 4, 64, 8, 2, 8) == -6
+    assert L.posit32_potrf(None, 0, 4, 64, 8, 4, None) == -7
+    # potrs(stream, uplo, n, nrhs, L, lda, B, ldb)
+    assert L.posit32_potrs(None, 3, 4, 2, 8, 4, 8, 2) == -2
+    assert L.posit32_potrs(None, 1, -4, 2, 8, 4, 8, 2) == -3
+    assert L.posit32_potrs(None, 1, 4, -2, 8, 4, 8, 2) == -4
+    assert L.posit32_potrs(None, 1, 4, 2, None, 4, 8, 2) == -5
+    assert L.posit32_potrs(None, 1, 4, 2, 8, 1, 8, 2) == -6
+    assert L.posit32_potrs(None, 0, 4, 2, 8, 4, None, 2) == -7
+    assert L.posit32_potrs(None, 1, 4, 2, 8, 4, 8, 1) == -8
+    assert L.posit32_potrs(None, 1, 0, 0, None, 1, None, 1) == 0
 
 
 def test_vbatched_argument_errors(L):

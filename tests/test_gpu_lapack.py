@@ -181,6 +181,92 @@ def test_solves_with_nar_and_zero_diagonal(P, n, nrhs, where):
     assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
 
 
+@pytest.mark.parametrize("where", ["u", "l", "b", "z"])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 1), (65, 70), (150, 5), (200, 2)])
+def test_transposed_and_upper_solves_with_nar_and_zero_diagonal(P, n, nrhs, where):
+    """getrs with op = T (A^T X = B) and the upper potrs (A = U^T U) on the
+    same special factors: bit for bit against the oracle."""
+    import torch
+    M, B, ipiv = _solve_case(n, nrhs, where)
+    X = O.getrs(M, ipiv, B, trans=True)
+    Bd = to_dev(B)
+    P.getrs(to_dev(M), torch.from_numpy(ipiv).cuda(), Bd, trans=True)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+    X = O.potrs(M, B, upper=True)
+    Bd = to_dev(B)
+    P.potrs(to_dev(M), Bd, upper=True)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+
+
+@pytest.mark.parametrize("n,nb", [(1, 256), (5, 256), (64, 64), (257, 256), (300, 64), (520, 256)])
+def test_getrs_trans_parity(P, n, nb):
+    """A^T X = B with the GPU's own factors: the oracle's transposed solve
+    on the same factors, bit for bit, with row interchanges everywhere."""
+    import torch
+    rng = np.random.default_rng(n * 17 + nb)
+    A = p32(rng.uniform(-1, 1, (n, n)) * 2.0 ** rng.integers(-3, 4, (n, n)))
+    gLU, gipiv, ginfo = _gpu_getrf(P, A, nb)
+    LU, ipiv, info = O.getrf(A, nb)
+    assert np.array_equal(gLU, LU) and np.array_equal(gipiv, ipiv) and ginfo == info
+    B = p32(rng.uniform(-1, 1, (n, 4)))
+    X = O.getrs(LU, ipiv, B, trans=True)
+    Bd = to_dev(B)
+    P.getrs(to_dev(gLU), torch.from_numpy(gipiv).cuda(), Bd, trans=True)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+
+
+def _gpu_potrf_upper(P, A, nb):
+    import torch
+    Ad = to_dev(A)
+    _, info = P.potrf(Ad, nb, upper=True)
+    torch.cuda.synchronize()
+    return from_dev(Ad), int(info.cpu().item())
+
+
+def _upper_input(n, seed, bad=None):
+    """The benchmark's SPD matrix with its strict lower triangle replaced by
+    unrelated patterns (an upper factorisation must not read or change it)."""
+    case = W.chol_case(n, nrhs=3)
+    A = case.A.copy()
+    if bad is not None:
+        A[bad, bad] = -50.0
+    Ap = p32(A)
+    rng = np.random.default_rng(seed)
+    il = np.tril_indices(n, -1)
+    Ap[il] = rng.integers(0, 1 << 32, il[0].size, dtype=np.uint64).astype(np.uint32)
+    return Ap, p32(case.b)
+
+
+@pytest.mark.parametrize("n,nb", [(1, 256), (7, 256), (33, 16), (100, 256), (256, 256), (300, 64),
+                                  (520, 256), (77, 1)])
+def test_potrf_potrs_upper_parity(P, n, nb):
+    A, B = _upper_input(n, 40 + n)
+    U, info = O.potrf(A, nb, upper=True)
+    gU, ginfo = _gpu_potrf_upper(P, A, nb)
+    assert ginfo == info == 0
+    assert np.array_equal(gU, U), _diff(gU, U)
+    il = np.tril_indices(n, -1)
+    assert np.array_equal(gU[il], A[il])                 # strict lower triangle unchanged
+    X = O.potrs(U, B, upper=True)
+    Bd = to_dev(B)
+    P.potrs(to_dev(gU), Bd, upper=True)
+    assert np.array_equal(from_dev(Bd), X), _diff(from_dev(Bd), X)
+    # the same bits as the lower factorisation of the mirrored matrix
+    Al = A.copy()
+    Al[il] = A.T[il]
+    gL, _ = _gpu_potrf(P, Al, nb)
+    assert np.array_equal(np.triu(gU), np.triu(gL.T))
+
+
+@pytest.mark.parametrize("bad", [5, 300, 511])
+def test_potrf_upper_not_positive_definite(P, bad):
+    A, _ = _upper_input(520, 90 + bad, bad=bad)
+    U, info = O.potrf(A, 256, upper=True)
+    gU, ginfo = _gpu_potrf_upper(P, A, 256)
+    assert ginfo == info == bad + 1
+    assert np.array_equal(gU, U), _diff(gU, U)
+
+
 def _perm(ipiv):
     """Row order of P A for LAPACK-style interchanges applied in order."""
     perm = np.arange(len(ipiv))

@@ -183,6 +183,25 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
  */
 int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                   int32_t* ipiv, int32_t* info);
+/*
+ * posit32_getrf_noalloc -- posit32_getrf (same arguments, validation, order
+ *   of operations and result bits) for callers that cannot allocate device
+ *   memory: code under stream capture by a harness that forbids hipMalloc,
+ *   tight serving loops, allocation-free runtimes.  It calls no hipMalloc,
+ *   hipMallocAsync, hipFree or other allocating routine: the pivot exchange
+ *   uses a file-scope device array of the library (1,056,768 bytes, the
+ *   workspace of up to 256 panel workgroups; the call caps each panel at that
+ *   many workgroups, so no n that posit32_getrf accepts is refused), which
+ *   every GPU the library runs on holds until the process ends.  Its device
+ *   address is looked up once per device on the first call (with that device
+ *   current); a failure of that lookup is returned as P32_E_HIP - e.  All
+ *   calls on one GPU share that GPU's array, and the call sets every word of
+ *   it before use: calls that overlap on one GPU (other streams, other host
+ *   threads) race on it and must be ordered by the caller.  Like
+ *   posit32_getrf it uses cooperative launches and is not capturable.
+ */
+int posit32_getrf_noalloc(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                          int32_t* ipiv, int32_t* info);
 int posit32_getrs(void* stream, int op, int64_t n, int64_t nrhs, const posit32_t* LU,
                   int64_t lda, const int32_t* ipiv, posit32_t* B, int64_t ldb);
 int posit32_potrf(void* stream, int uplo, int64_t n, int64_t nb, posit32_t* A, int64_t lda,

@@ -77,6 +77,18 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
   return p32::launch_getrf((hipStream_t)stream, n, nb, A, lda, ipiv, info);
 }
 
+int posit32_getrf_noalloc(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                          int32_t* ipiv, int32_t* info) {
+  if (n < 0) return -2;
+  if (nb < 1 || nb > 256) return -3;
+  if (n > 0 && A == nullptr) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && ipiv == nullptr) return -6;
+  if (info == nullptr) return -7;
+  if (n > 0xFFFFFE) return -2;                    // pivot rows are carried in 24 bits
+  return p32::launch_getrf_noalloc((hipStream_t)stream, n, nb, A, lda, ipiv, info);
+}
+
 int posit32_getrs(void* stream, int op, int64_t n, int64_t nrhs, const posit32_t* LU, int64_t lda,
                   const int32_t* ipiv, posit32_t* B, int64_t ldb) {
   if (op != P32_NOTRANS && op != P32_TRANS) return -2;

@@ -27,6 +27,8 @@
 // k-step arithmetic where it is proven exact (chain_update, p32_chain.hpp).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "p32_chain.hpp"
 #include "p32_device.hpp"
 #include "p32_gemm_tile.hpp"
@@ -778,38 +780,48 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t count, unsigned l
 #define P32_PANEL_MIN_ROWS 4      // fewest panel rows per workgroup
 #endif
 
-int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
-                 int32_t* info) {
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
-  if (n == 0) return launch_status();
-  int dev = 0, cus = 0, per_cu_lds = 0, per_cu_glb = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu_lds, reinterpret_cast<const void*>(&lu_panel_kernel<true>), kPanelThreads, 0);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu_glb, reinterpret_cast<const void*>(&lu_panel_kernel<false>), kPanelThreads, 0);
-  if (e != hipSuccess) return -1000 - (int)e;
-  if (per_cu_lds < 1 || per_cu_glb < 1) return -1000 - (int)hipErrorCooperativeLaunchTooLarge;
-  // at most one workgroup per compute unit (and per slot-reading thread),
-  // at least 8 rows per workgroup
-  int64_t gmax = cus < 1 ? 1 : cus;
-  if (gmax > kPanelThreads) gmax = kPanelThreads;
+// The panel's pivot exchange: per workgroup two key slots and two candidate
+// rows of 8-byte tagged words, plus two copies of row c -- sized for gmax
+// workgroups.
+static constexpr size_t getrf_ws_bytes(int64_t gmax) {
+  return (size_t)2 * gmax * sizeof(unsigned long long) +
+         (size_t)2 * gmax * kMaxNB * sizeof(unsigned long long) +
+         (size_t)2 * kMaxNB * sizeof(unsigned long long);
+}
 
+// Most workgroups of one panel: one per compute unit (the slot-reading loop
+// takes one thread per workgroup), capped at gcap.
+static int getrf_setup(int64_t gcap, int* cus, int* per_cu_lds, int* per_cu_glb, int64_t* gmax) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu_lds, reinterpret_cast<const void*>(&lu_panel_kernel<true>), kPanelThreads, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu_glb, reinterpret_cast<const void*>(&lu_panel_kernel<false>), kPanelThreads, 0);
+  if (e != hipSuccess) return -1000 - (int)e;
+  if (*per_cu_lds < 1 || *per_cu_glb < 1) return -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+  int64_t g = *cus < 1 ? 1 : *cus;
+  if (g > kPanelThreads) g = kPanelThreads;
+  if (g > gcap) g = gcap;
+  *gmax = g;
+  return 0;
+}
+
+// getrf on a caller-provided workspace of getrf_ws_bytes(gmax) bytes (every
+// word is set before the first panel, so its previous contents do not matter)
+static int getrf_run(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                     int32_t* info, char* ws, int64_t gmax, int cus, int per_cu_lds, int per_cu_glb) {
   const size_t slot_bytes = (size_t)2 * gmax * sizeof(unsigned long long);
   const size_t row_bytes = (size_t)2 * gmax * kMaxNB * sizeof(unsigned long long);
-  const size_t rowc_bytes = (size_t)2 * kMaxNB * sizeof(unsigned long long);
-  char* ws = nullptr;
-  e = hipMallocAsync((void**)&ws, slot_bytes + row_bytes + rowc_bytes, s);
-  if (e != hipSuccess) return -1000 - (int)e;
   unsigned long long* slot = reinterpret_cast<unsigned long long*>(ws);
   unsigned long long* crow = reinterpret_cast<unsigned long long*>(ws + slot_bytes);
   unsigned long long* rowc = reinterpret_cast<unsigned long long*>(ws + slot_bytes + row_bytes);
   // all ones: slot tag 0xFF matches neither column 0 nor column 1 (every slot
   // is written before the panel's column 255), row-copy tag 0xFFFFFFFF no column
-  const int64_t ws_words = (int64_t)((slot_bytes + row_bytes + rowc_bytes) / sizeof(unsigned long long));
+  const int64_t ws_words = (int64_t)(getrf_ws_bytes(gmax) / sizeof(unsigned long long));
   hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((ws_words + 255) / 256)), dim3(256), 0, s, slot,
                      ws_words, ~0ull);
   int rc = launch_status();
@@ -828,7 +840,7 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
     void* args[] = {&A, &lda, &n, &j, &jb_i, &R_i, &slot, &crow, &rowc, &ipiv, &info};
     const void* fn = lds ? reinterpret_cast<const void*>(&lu_panel_kernel<true>)
                          : reinterpret_cast<const void*>(&lu_panel_kernel<false>);
-    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, s);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, s);
     if (e != hipSuccess) {
       rc = -1000 - (int)e;
       break;
@@ -845,9 +857,75 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
     }
     if (rc == 0) rc = launch_status();
   }
+  return rc;
+}
+
+int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                 int32_t* info) {
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
+  if (n == 0) return launch_status();
+  int cus = 0, per_cu_lds = 0, per_cu_glb = 0;
+  int64_t gmax = 0;
+  int rc = getrf_setup(kPanelThreads, &cus, &per_cu_lds, &per_cu_glb, &gmax);
+  if (rc != 0) return rc;
+  char* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, getrf_ws_bytes(gmax), s);
+  if (e != hipSuccess) return -1000 - (int)e;
+  rc = getrf_run(s, n, nb, A, lda, ipiv, info, ws, gmax, cus, per_cu_lds, per_cu_glb);
   e = hipFreeAsync(ws, s);
   if (rc != 0) return rc;
   if (e != hipSuccess) return -1000 - (int)e;
+  return launch_status();
+}
+
+// ---- allocation-free getrf ---------------------------------------------------
+// The workspace of getrf in a file-scope device array instead of a
+// stream-ordered allocation: sized for kScratchGroups panel workgroups (the
+// call caps the panel at that many workgroups, more rows each), 1,056,768
+// bytes, held by every GPU the library runs on until the process ends.  In
+// host code `scratch` only names the symbol; its device address is taken
+// once per device with hipGetSymbolAddress (with that device current) and
+// kept in g_scratch, which is what the kernels receive.  Every call on a GPU
+// shares that GPU's array.
+constexpr int64_t kScratchGroups = 256;
+constexpr size_t kScratchBytes = getrf_ws_bytes(kScratchGroups);
+static_assert(kScratchBytes == 1056768, "the size the library header states");
+static __device__ __align__(256) unsigned long long scratch[kScratchBytes / 8];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices];
+
+static int scratch_address(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return -1000 - (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return -1000 - (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return -1000 - (int)e;
+    if (p == nullptr) return -1000 - (int)hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch[dev]);
+  return 0;
+}
+
+int launch_getrf_noalloc(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                         int32_t* info) {
+  char* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc != 0) return rc;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
+  if (n == 0) return launch_status();
+  int cus = 0, per_cu_lds = 0, per_cu_glb = 0;
+  int64_t gmax = 0;
+  rc = getrf_setup(kScratchGroups, &cus, &per_cu_lds, &per_cu_glb, &gmax);
+  if (rc != 0) return rc;
+  rc = getrf_run(s, n, nb, A, lda, ipiv, info, ws, gmax, cus, per_cu_lds, per_cu_glb);
+  if (rc != 0) return rc;
   return launch_status();
 }
 

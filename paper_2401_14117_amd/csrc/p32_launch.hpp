@@ -32,6 +32,9 @@ int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, cons
 
 int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                  int32_t* info);
+// getrf on the library's file-scope device scratch (no allocation)
+int launch_getrf_noalloc(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                         int32_t* info);
 // trans: solve A^T X = B;  upper: A = U^T U with U in the upper triangle
 int launch_getrs(hipStream_t s, int trans, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
                  const int32_t* ipiv, uint32_t* B, int64_t ldb);

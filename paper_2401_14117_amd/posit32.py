@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.posit32_to_f64.argtypes = [vp, i64, vp, vp]
     L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
     L.posit32_getrf.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.posit32_getrf_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.posit32_getrf_noalloc.restype = i32
     L.posit32_getrs.argtypes = [vp, i32, i64, i64, vp, i64, vp, vp, i64]
     L.posit32_potrf.argtypes = [vp, i32, i64, i64, vp, i64, vp]
     L.posit32_potrs.argtypes = [vp, i32, i64, i64, vp, i64, vp, i64]

@@ -82,6 +82,14 @@ def test_factorisation_argument_errors(L):
     assert L.posit32_getrf(None, 4, 64, 8, 3, 8, 8) == -5
     assert L.posit32_getrf(None, 4, 64, 8, 4, None, 8) == -6
     assert L.posit32_getrf(None, 4, 64, 8, 4, 8, None) == -7
+    # the allocation-free getrf validates exactly like getrf
+    assert L.posit32_getrf_noalloc(None, -1, 256, 8, 1, 8, 8) == -2
+    assert L.posit32_getrf_noalloc(None, 4, 257, 8, 4, 8, 8) == -3
+    assert L.posit32_getrf_noalloc(None, 4, 64, None, 4, 8, 8) == -4
+    assert L.posit32_getrf_noalloc(None, 4, 64, 8, 3, 8, 8) == -5
+    assert L.posit32_getrf_noalloc(None, 4, 64, 8, 4, None, 8) == -6
+    assert L.posit32_getrf_noalloc(None, 4, 64, 8, 4, 8, None) == -7
+    assert L.posit32_getrf_noalloc(None, 1 << 24, 64, 8, 1 << 24, 8, 8) == -2
     # getrs(stream, op, n, nrhs, LU, lda, ipiv, B, ldb)
     assert L.posit32_getrs(None, 2, 4, 1, 8, 4, 8, 8, 1) == -2
     assert L.posit32_getrs(None, -1, 4, 1, 8, 4, 8, 8, 1) == -2

@@ -612,6 +612,77 @@ def run_cpu_baseline(case, budget_s: float):
                       f"{threads} OpenMP threads"}
 
 
+def _cpu_info() -> dict:
+    """The GPU machine's host CPU: model, the cores this process may run on, and
+    the OpenMP threads the oracle uses."""
+    import oracle
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)),
+            "omp_threads": oracle.num_threads()}
+
+
+def run_cpu_single_thread(budget_s: float) -> dict:
+    """The oracle on one thread at n = 1024 (square Rgemm case), sampled
+    outputs for about budget_s seconds."""
+    import ctypes
+    import oracle
+    from paper_2401_14117_amd import workloads as W
+    oracle.lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    before = oracle.num_threads()
+    gomp.omp_set_num_threads(1)
+    try:
+        r = run_cpu_baseline(W.gemm_square(1024), budget_s)
+    finally:
+        gomp.omp_set_num_threads(before)
+    return {"value": r["value"], "unit": "Gpops/s", "threads": 1, "sample": r["sample"]}
+
+
+def run_extras(args, dev) -> dict:
+    """The other two clauses of the metric, measured in the same run: the
+    20,000-system batched factor + solve (one persistent launch, replayed
+    from a hipGraph) for LU and Cholesky, and the LU request queue under
+    Poisson arrivals at one rate with the same requests one at a time."""
+    import argparse as _ap
+    out = {}
+    bargs = _ap.Namespace(**vars(args))
+    bargs.cpu_budget = 0.0
+    bargs.single_count = args.extras_single
+    bargs.steps, bargs.warmup = 3, 1
+    for kind in ("lu", "chol"):
+        r = run_batch_bench(f"batch_{kind}", bargs, dev)
+        c = r["config"]
+        one = c["one_at_a_time"]
+        out[f"batch_{kind}"] = {
+            "solves_per_s": r["value"], "ms_per_batch": r["ms_per_step"], "systems": c["count"],
+            "factor_gpops": c["factor_gpops"], "graph_bit_identical_to_eager": c["graph_bit_identical_to_eager"],
+            "one_at_a_time_solves_per_s": one["solves_per_s"] if one else None,
+            "one_at_a_time_bit_identical": one["bit_identical_to_batched"] if one else None,
+            "setup_s": c["setup_s"]}
+    sargs = _ap.Namespace(**vars(args))
+    sargs.qps = [args.extras_qps]
+    line = run_serve_bench(sargs, dev, "lu")[0]
+    c = line["config"]
+    same = c["same_requests"] or {}
+    out["serve_lu"] = {
+        "qps": c["qps"], "requests": c["requests"], "solves_per_s": line["value"],
+        "p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "p50_ms_small_n": c["p50_ms_small_n"],
+        "p99_ms_small_n": c["p99_ms_small_n"], "mean_batch": c["mean_batch"], "failed": c["failed"],
+        "all_at_once_solves_per_s": same.get("queue_all_at_once", {}).get("solves_per_s"),
+        "one_at_a_time_solves_per_s": same.get("one_at_a_time", {}).get("solves_per_s"),
+        "bit_identical": bool(same.get("queue_all_at_once", {}).get("bit_identical_to_served")
+                              and same.get("one_at_a_time", {}).get("bit_identical_to_served"))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -640,6 +711,13 @@ def main() -> int:
     ap.add_argument("--nb", type=int, default=256, help="block size of the factorisations")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="Rgemm workloads: also measure the batched (LU, Cholesky) and served (LU) "
+                         "workloads and the one-thread oracle, reported in the same line (0: skip)")
+    ap.add_argument("--extras-qps", type=float, default=150.0,
+                    help="arrival rate of the served workload measured with --extras")
+    ap.add_argument("--extras-single", type=int, default=100,
+                    help="batched systems also solved one at a time with --extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (for HBM counter scaling) and exit")
     args = ap.parse_args()
@@ -741,9 +819,12 @@ def main() -> int:
     cpu = None
     if args.cpu_budget > 0 and args.trans == "nn":
         cpu = run_cpu_baseline(case, args.cpu_budget)
+        cpu.update(_cpu_info())
+        cpu["single_thread_n1024"] = run_cpu_single_thread(min(args.cpu_budget, 5.0))
+    extras = run_extras(args, dev) if args.extras and args.trans == "nn" and case.name == "square_n8192" else None
 
     out = {
-        "metric": "Posit32 Rgemm Gpops/s at n=8192 (% int-VALU peak)",
+        "metric": "Posit32 Rgemm Gpops/s at n=8192 (% int-VALU peak); batched solves/s; p50/p99 latency",
         "value": round(gpops, 2),
         "unit": "Gpops/s",
         "n_gpus": 1,
@@ -764,6 +845,9 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if extras is not None:
+        out["batched"] = {k: v for k, v in extras.items() if k.startswith("batch_")}
+        out["serving"] = extras["serve_lu"]
     print(json.dumps(out))
     return 0
 

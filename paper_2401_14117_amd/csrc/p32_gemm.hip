@@ -76,6 +76,45 @@ gemm_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int
   gemm_tile<TA, TB, LOWER, CHAIN>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, i0, j0, sm);
 }
 
+// The same tile computation with a smaller workgroup tile (MidTile: 32 x 32
+// outputs per 256 threads; SmallTile: 8 x 8 per 64 threads), for shapes whose
+// 64 x 32 tiles would leave compute units idle.  Every output still gets the
+// one order of operations, so the bits do not depend on the tile shape.
+template <bool TA, bool TB, class S>
+__global__ void __launch_bounds__(S::NT)
+gemm_shape_kernel(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A, int64_t lda,
+                  const uint32_t* __restrict__ B, int64_t ldb, uint32_t* __restrict__ C, int64_t ldc,
+                  uint32_t alpha, uint32_t beta) {
+  __shared__ TileLdsT<S> sm;
+  int64_t i0, j0;
+  tile_origin<S>(m, n, blockIdx.x, i0, j0);
+  gemm_tile<TA, TB, false, false, false, P32_GEMM_UNROLL, S>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta,
+                                                             i0, j0, sm);
+}
+
+template <class S>
+static int64_t tile_count(int64_t m, int64_t n) {
+  return ((m + S::BM - 1) / S::BM) * ((n + S::BN - 1) / S::BN);
+}
+
+// Tile shape of a plain Rgemm launch: 64 x 32 tiles while they give every
+// compute unit at least four, else 32 x 32 tiles while those give every
+// compute unit at least two, else 8 x 8 tiles.  0 big, 1 mid, 2 small.
+static int pick_shape(int64_t m, int64_t n) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+      cus = c;
+    else
+      cus = 256;
+  }
+  if (tile_count<BigTile>(m, n) >= 4 * (int64_t)cus) return 0;
+  if (tile_count<MidTile>(m, n) >= 2 * (int64_t)cus) return 1;
+  return 2;
+}
+
 // alpha == 0 or k == 0: C = (beta == 0) ? 0 : beta*C
 __global__ void scale_c_kernel(int64_t m, int64_t n, uint32_t* __restrict__ C, int64_t ldc,
                                uint32_t beta, bool lower, const int32_t* __restrict__ skip) {
@@ -110,6 +149,24 @@ int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t 
 #define P32_LAUNCH(TA_, TB_, LO_) \
   hipLaunchKernelGGL((gemm_kernel<TA_, TB_, LO_, false>), grid, block, 0, s, m, n, k, A, lda, B, ldb, \
                      C, ldc, alpha, beta, skip)
+  const int shape = lower ? 0 : pick_shape(m, n);
+  if (shape != 0) {
+    const int64_t t = shape == 1 ? tile_count<MidTile>(m, n) : tile_count<SmallTile>(m, n);
+    const int nt = shape == 1 ? MidTile::NT : SmallTile::NT;
+    if (t * nt >= ((int64_t)1 << 32)) return -4;
+#define P32_LAUNCH_S(TA_, TB_, S_) \
+    hipLaunchKernelGGL((gemm_shape_kernel<TA_, TB_, S_>), dim3((unsigned)t), dim3(S_::NT), 0, s, m, n, k, A, \
+                       lda, B, ldb, C, ldc, alpha, beta)
+#define P32_LAUNCH_T(TA_, TB_) \
+    if (shape == 1) P32_LAUNCH_S(TA_, TB_, MidTile); else P32_LAUNCH_S(TA_, TB_, SmallTile)
+    if (!ta && !tb) { P32_LAUNCH_T(false, false); }
+    else if (!ta && tb) { P32_LAUNCH_T(false, true); }
+    else if (ta && !tb) { P32_LAUNCH_T(true, false); }
+    else { P32_LAUNCH_T(true, true); }
+#undef P32_LAUNCH_T
+#undef P32_LAUNCH_S
+    return launch_status();
+  }
   if (lower) {
     if (!ta && tb) P32_LAUNCH(false, true, true);
     else return -1;                                   // only the Cholesky form is needed

@@ -32,8 +32,28 @@ namespace p32 {
 #define P32_GEMM_BK 16            // k-tile depth staged per barrier pair
 #endif
 
-constexpr int TM = P32_GEMM_TM, TN = P32_GEMM_TN, NT = 256, BK = P32_GEMM_BK;
-constexpr int BM = 16 * TM, BN = 16 * TN;   // 16 x 16 threads per workgroup
+// Shape of a workgroup tile: TY x TX threads, each owning a TM x TN
+// micro-tile of C, so the workgroup owns BM x BN = (TY TM) x (TX TN)
+// outputs; k-tiles of BK.
+// PREFETCH: the raw words of the next k-tile are loaded into registers
+// before the current k-tile is computed (fewer resident waves have to hide
+// the load latency); off for the big tile, whose register budget is spent.
+template <int TM_, int TN_, int TX_, int TY_, bool PREFETCH_>
+struct TileShape {
+  static constexpr int TM = TM_, TN = TN_, TX = TX_, TY = TY_;
+  static constexpr int NT = TX * TY, BM = TY * TM, BN = TX * TN, BK = P32_GEMM_BK;
+  static constexpr bool PREFETCH = PREFETCH_;
+};
+// 64 x 32 outputs per 256 threads: the Rgemm of large shapes, the batched
+// kernels and the factorisations' updates
+using BigTile = TileShape<P32_GEMM_TM, P32_GEMM_TN, 16, 16, false>;
+// 32 x 32 per 256 threads and 8 x 8 per 64 threads: shapes too small to give
+// every compute unit several big tiles
+using MidTile = TileShape<2, 2, 16, 16, true>;
+using SmallTile = TileShape<1, 1, 8, 8, true>;
+
+constexpr int TM = BigTile::TM, TN = BigTile::TN, NT = BigTile::NT, BK = BigTile::BK;
+constexpr int BM = BigTile::BM, BN = BigTile::BN;
 constexpr unsigned GROUP_M = 8;             // tile rows per group of the tile order
 constexpr int EB = 8192 + 128;           // exponent bias inside the kernel
 constexpr int kEZeroB = kEZero + EB;     // biased exponent of zero (> 0)
@@ -188,10 +208,11 @@ __device__ __forceinline__ int64_t uniform64(int64_t u) {
 
 // One k step for the thread's TM x TN accumulators.  Flagged lanes redo the
 // whole step on the exact path.
-template <bool CHECKED>
-__device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restrict__ Arow,
+template <bool CHECKED, class S = BigTile>
+__device__ __forceinline__ void k_step(win (&acc)[S::TM][S::TN], const int2* __restrict__ Arow,
                                        const int2* __restrict__ Brow, const lut_t* __restrict__ lut,
                                        int tx, int ty) {
+  constexpr int TM = S::TM, TN = S::TN;
   int2 a[TM], b[TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i) a[i] = Arow[ty * TM + i];
@@ -239,20 +260,24 @@ __device__ __forceinline__ void k_step(win (&acc)[TM][TN], const int2* __restric
 // REVK: the k index runs backwards, p = k-1, ..., 0 (the backward
 // substitutions of the solves, whose updates come in descending column order).
 // LDS of one tile computation; the caller declares it once per kernel
-struct TileLds {
-  int2 As[BK][BM];   // stage_a of op(A)(i0 + i, p0 + p)
-  int2 Bs[BK][BN];   // stage_b of op(B)(p0 + p, j0 + j)
-  lut_t lut[256];    // rounding parameters of scales -124..131
-  int rowNaR[BM], colNaR[BN];
+template <class S>
+struct TileLdsT {
+  int2 As[S::BK][S::BM];   // stage_a of op(A)(i0 + i, p0 + p)
+  int2 Bs[S::BK][S::BN];   // stage_b of op(B)(p0 + p, j0 + j)
+  lut_t lut[256];          // rounding parameters of scales -124..131
+  int rowNaR[S::BM], colNaR[S::BN];
 };
+using TileLds = TileLdsT<BigTile>;
 
 // UNROLL: k-steps of a proven k-tile unrolled per loop iteration (code size
 // against loop overhead; the Rgemm kernel unrolls the whole k-tile).
-template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK = false, int UNROLL = P32_GEMM_UNROLL>
+template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK = false, int UNROLL = P32_GEMM_UNROLL,
+          class S = BigTile>
 __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const uint32_t* __restrict__ A,
                                           int64_t lda, const uint32_t* __restrict__ B, int64_t ldb,
                                           uint32_t* __restrict__ C, int64_t ldc, uint32_t alpha,
-                                          uint32_t beta, int64_t i0, int64_t j0, TileLds& sm) {
+                                          uint32_t beta, int64_t i0, int64_t j0, TileLdsT<S>& sm) {
+  constexpr int TM = S::TM, TN = S::TN, NT = S::NT, BK = S::BK, BM = S::BM, BN = S::BN;
   auto& As = sm.As;
   auto& Bs = sm.Bs;
   auto& lut = sm.lut;
@@ -260,12 +285,14 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
   auto& colNaR = sm.colNaR;
 
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+  const int tx = tid % S::TX, ty = tid / S::TX;
   if (LOWER && i0 + BM - 1 < j0) return;          // tile entirely above the diagonal
   __syncthreads();                                // LDS of a previous tile no longer in use
   if (tid < BM) rowNaR[tid] = 0;
   if (tid < BN) colNaR[tid] = 0;
-  lut[tid] = make_lut_entry(tid);   // NT == 256 entries
+  static_assert(256 % NT == 0, "table fill");
+#pragma unroll
+  for (int e = 0; e < 256; e += NT) lut[e + tid] = make_lut_entry(e + tid);
 
   win acc[TM][TN];
   uint32_t cnar = 0;            // CHAIN: bit i*TN+j set when C_ij starts as NaR
@@ -302,10 +329,74 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
   // index is below 64), compared with 32-bit per-thread indices
   const int rem_m = (int)min(m - i0, (int64_t)BM), rem_n = (int)min(n - j0, (int64_t)BN);
 
+  // PREFETCH: raw words of this thread's share of the next k-tile
+  constexpr int LA = (BM * BK) / NT, LB = (BN * BK) / NT;
+  uint32_t ra[S::PREFETCH ? LA : 1], rb[S::PREFETCH ? LB : 1];
+  // op(A)(i0 + ii, p0 + pp) and op(B)(p0 + pp, j0 + jj) for element l:
+  // 0 beyond k, 1.0 beyond m or n (results discarded)
+  auto fetch_a = [&](int64_t q0, int l) -> uint32_t {
+    const int ii = TA ? a_c : a_r + l * (NT / BK);
+    const int pp = TA ? a_r + l * (NT / BM) : a_c;
+    if (q0 + pp >= k) return 0u;
+    if (ii >= rem_m) return kOne;
+    if (REVK) {
+      const int64_t gi = i0 + ii, gk = k - 1 - (q0 + pp);
+      return TA ? A[gk * lda + gi] : A[gi * lda + gk];
+    }
+    const int64_t u = TA ? (q0 + l * (NT / BM)) * lda + i0 : (i0 + l * (NT / BK)) * lda + q0;
+    return A[uniform64(u) + a_off];
+  };
+  auto fetch_b = [&](int64_t q0, int l) -> uint32_t {
+    const int jj = TB ? b_r + l * (NT / BK) : b_c;
+    const int pp = TB ? b_c : b_r + l * (NT / BN);
+    if (q0 + pp >= k) return 0u;
+    if (jj >= rem_n) return kOne;
+    if (REVK) {
+      const int64_t gj = j0 + jj, gk = k - 1 - (q0 + pp);
+      return TB ? B[gj * ldb + gk] : B[gk * ldb + gj];
+    }
+    const int64_t u = TB ? (j0 + l * (NT / BK)) * ldb + q0 : (q0 + l * (NT / BN)) * ldb + j0;
+    return B[uniform64(u) + b_off];
+  };
+  if constexpr (S::PREFETCH) {
+#pragma unroll
+    for (int l = 0; l < LA; ++l) ra[l] = fetch_a(0, l);
+#pragma unroll
+    for (int l = 0; l < LB; ++l) rb[l] = fetch_b(0, l);
+  }
+
   for (int64_t p0 = 0; p0 < k; p0 += BK) {
     int my_ok = 1;
     const int rem_k = (int)min(k - p0, (int64_t)BK);
     __syncthreads();
+    if constexpr (S::PREFETCH) {
+#pragma unroll
+      for (int l = 0; l < LA; ++l) {
+        const int ii = TA ? a_c : a_r + l * (NT / BK);
+        const int pp = TA ? a_r + l * (NT / BM) : a_c;
+        uint32_t v = ra[l];
+        if (v == kNaR) { rowNaR[ii] = 1; v = kOne; }
+        const dec d = decode(v);
+        my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
+        As[pp][ii] = stage_a(d, CHAIN);
+      }
+#pragma unroll
+      for (int l = 0; l < LB; ++l) {
+        const int jj = TB ? b_r + l * (NT / BK) : b_c;
+        const int pp = TB ? b_c : b_r + l * (NT / BN);
+        uint32_t v = rb[l];
+        if (v == kNaR) { colNaR[jj] = 1; v = kOne; }
+        const dec d = decode(v);
+        my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
+        Bs[pp][jj] = stage_b(d);
+      }
+      if (p0 + BK < k) {
+#pragma unroll
+        for (int l = 0; l < LA; ++l) ra[l] = fetch_a(p0 + BK, l);
+#pragma unroll
+        for (int l = 0; l < LB; ++l) rb[l] = fetch_b(p0 + BK, l);
+      }
+    } else {
 #pragma unroll
     for (int l = 0; l < (BM * BK) / NT; ++l) {
       // op(A)(i0 + ii, p0 + pp) with ii, pp this thread's element l
@@ -348,6 +439,7 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
       my_ok &= (d.s != 0) & ((unsigned)(d.sc + 53) <= 102u);
       Bs[pp][jj] = stage_b(d);
     }
+    }
     // Block-uniform choice of the inner loop for this k-tile.  The unchecked
     // loop is exact when every staged operand is nonzero with scale in
     // [-53, 49] (products then have scales in [-106, 99]) and every
@@ -366,20 +458,20 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
     const bool safe = __syncthreads_and(my_ok);
 
     if (p0 == 0) {        // first step: accumulators not yet tested, use the checked path
-      k_step<true>(acc, As[0], Bs[0], lut, tx, ty);
+      k_step<true, S>(acc, As[0], Bs[0], lut, tx, ty);
       if (safe) {
 #pragma unroll 1
-        for (int p = 1; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
+        for (int p = 1; p < BK; ++p) k_step<false, S>(acc, As[p], Bs[p], lut, tx, ty);
       } else {
 #pragma unroll 1
-        for (int p = 1; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
+        for (int p = 1; p < BK; ++p) k_step<true, S>(acc, As[p], Bs[p], lut, tx, ty);
       }
     } else if (safe) {
       P32_UNROLL_(UNROLL)
-      for (int p = 0; p < BK; ++p) k_step<false>(acc, As[p], Bs[p], lut, tx, ty);
+      for (int p = 0; p < BK; ++p) k_step<false, S>(acc, As[p], Bs[p], lut, tx, ty);
     } else {
 #pragma unroll 1
-      for (int p = 0; p < BK; ++p) k_step<true>(acc, As[p], Bs[p], lut, tx, ty);
+      for (int p = 0; p < BK; ++p) k_step<true, S>(acc, As[p], Bs[p], lut, tx, ty);
     }
   }
   __syncthreads();
@@ -410,7 +502,9 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
 // of GROUP_M tile rows column by column, so the tiles that are resident on an
 // XCD at one time form a compact block of C and share their A and B panels in
 // that XCD's L2.
+template <class S = BigTile>
 __device__ __forceinline__ void tile_origin(int64_t m, int64_t n, unsigned g, int64_t& i0, int64_t& j0) {
+  constexpr int BM = S::BM, BN = S::BN;
   const unsigned nrow = (unsigned)((m + BM - 1) / BM), ncol = (unsigned)((n + BN - 1) / BN);
   const unsigned G = nrow * ncol;
   if (G % 8u == 0u) g = (g % 8u) * (G / 8u) + g / 8u;

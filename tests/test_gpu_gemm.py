@@ -1,4 +1,6 @@
 """GPU parity of Rgemm (posit32_gemm) against the oracle, bit for bit."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -52,6 +54,34 @@ def test_ragged_scaled(P, m, n, k, ta, tb):
     if tb:
         B = np.ascontiguousarray(B.reshape(k, n).T)
     al, be = O.from_double(-1.0 if k % 2 else 1.5), O.from_double(1.0 if m % 2 else -0.25)
+    want = O.gemm(A, B, C, al, be, transa=bool(ta), transb=bool(tb))
+    got = _run(P, A, B, C, al, be, bool(ta), bool(tb))
+    assert np.array_equal(got, want), _report(got, want)
+
+
+# The library picks the workgroup tile from the output shape: 64 x 32 tiles
+# when there are at least four per compute unit (1024 on MI355X), else 32 x 32
+# tiles when there are at least two per compute unit, else 8 x 8 tiles.  The
+# shapes below land in each regime, ragged in every dimension.
+@pytest.mark.parametrize("m,n,k,ta,tb,regime", [
+    (2049, 1057, 37, 0, 0, "64x32"), (1057, 2049, 19, 1, 1, "64x32"), (1100, 1901, 5, 0, 1, "64x32"),
+    (700, 801, 45, 0, 0, "32x32"), (801, 700, 33, 1, 0, "32x32"), (769, 735, 17, 1, 1, "32x32"),
+    (511, 513, 70, 0, 1, "8x8"), (9, 2000, 65, 0, 0, "8x8"), (300, 7, 100, 1, 0, "8x8"),
+])
+def test_tile_regimes(P, m, n, k, ta, tb, regime):
+    """Each workgroup-tile regime of the Rgemm launch (picked from m and n),
+    all transposes, NaR/zero sprinkle, against the oracle bit for bit."""
+    big = -(-m // 64) * -(-n // 32)
+    mid = -(-m // 32) * -(-n // 32)
+    want_regime = "64x32" if big >= 1024 else ("32x32" if mid >= 512 else "8x8")
+    assert want_regime == regime
+    case = W.gemm_scaled(m, n, k, seed=m + 3 * n + 7 * k, sprinkle=1e-4)
+    A, B, C, _, _ = case_patterns(case)
+    if ta:
+        A = np.ascontiguousarray(A.reshape(m, k).T)
+    if tb:
+        B = np.ascontiguousarray(B.reshape(k, n).T)
+    al, be = O.from_double(-1.0), O.from_double(1.0 if k % 2 else 0.5)
     want = O.gemm(A, B, C, al, be, transa=bool(ta), transb=bool(tb))
     got = _run(P, A, B, C, al, be, bool(ta), bool(tb))
     assert np.array_equal(got, want), _report(got, want)
@@ -141,6 +171,8 @@ def _sampled_rows_cols(case, rng, count):
     cols = list(rng.integers(0, n, count)) + [0, n - 1]
     # every row/column that holds a sprinkled special value
     for mat, axis in ((case.A, 0), (case.B, 1)):
+        if mat.zero_mask is None:
+            continue
         hit = np.argwhere(mat.zero_mask | mat.nar_mask)
         for ix in hit[:32]:
             if axis == 0:
@@ -150,13 +182,35 @@ def _sampled_rows_cols(case, rng, count):
     return np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64)
 
 
-@pytest.mark.parametrize("which", ["square_8192", "trailing_j1"])
+def _case(which):
+    if which == "square_8192":
+        return W.gemm_square(8192)
+    if which.startswith("trailing_j"):
+        return W.gemm_trailing(int(which[len("trailing_j"):]))
+    if which.startswith("normal_sigma"):
+        return W.gemm_normal(8192, float(which[len("normal_sigma"):]))
+    raise ValueError(which)
+
+
+@functools.lru_cache(maxsize=1)
+def _square8192():
+    case = W.gemm_square(8192)
+    return (case,) + case_patterns(case)
+
+
+@pytest.mark.parametrize("which", ["square_8192", "trailing_j1", "trailing_j8", "trailing_j16",
+                                   "trailing_j24", "trailing_j30", "normal_sigma1e+06"])
 def test_full_size_sampled(P, which):
-    """Full-size workloads in the benchmark's launch configuration, checked on
-    sampled outputs that the oracle computes one by one."""
+    """Full-size workloads in the benchmark's launch configuration (the square
+    n = 8192 case, the LU trailing-update shapes 8192 - 256 j with k = 256,
+    the paper's largest-magnitude normal inputs), checked on sampled outputs
+    that the oracle computes one by one."""
     import torch
-    case = W.gemm_square(8192) if which == "square_8192" else W.gemm_trailing(1)
-    A, B, C, al, be = case_patterns(case)
+    if which == "square_8192":
+        case, A, B, C, al, be = _square8192()
+    else:
+        case = _case(which)
+        A, B, C, al, be = case_patterns(case)
     Cd = to_dev(C)
     P.gemm(to_dev(A), to_dev(B), Cd, al, be)
     torch.cuda.synchronize()
@@ -166,3 +220,31 @@ def test_full_size_sampled(P, which):
     want = O.gemm_entries(A, B, rows, cols, C[rows, cols], al, be)
     bad = np.nonzero(got[rows, cols] != want)[0]
     assert bad.size == 0, [(rows[i], cols[i], hex(got[rows[i], cols[i]]), hex(want[i])) for i in bad[:6]]
+
+
+def test_full_size_transposes(P):
+    """NT, TN and TT at n = 8192 on the square case's matrices stored
+    transposed: op(A) op(B) is the same product, so every one of the 67M
+    outputs must equal the NN launch's, and sampled outputs equal the
+    oracle's transposed evaluation."""
+    import torch
+    case, A, B, C, al, be = _square8192()
+    n = case.n
+    Cd = to_dev(C)
+    Ad, Bd = to_dev(A), to_dev(B)
+    P.gemm(Ad, Bd, Cd, al, be)
+    torch.cuda.synchronize()
+    nn = from_dev(Cd)
+    At, Bt = np.ascontiguousarray(A.T), np.ascontiguousarray(B.T)
+    Atd, Btd = to_dev(At), to_dev(Bt)
+    rng = np.random.default_rng(28)
+    rows, cols = _sampled_rows_cols(case, rng, 100)
+    for ta, tb in ((False, True), (True, False), (True, True)):
+        Cd = to_dev(C)
+        P.gemm(Atd if ta else Ad, Btd if tb else Bd, Cd, al, be, transa=ta, transb=tb)
+        torch.cuda.synchronize()
+        got = from_dev(Cd)
+        assert np.array_equal(got, nn), (ta, tb, _report(got, nn))
+        want = O.gemm_entries(At if ta else A, Bt if tb else B, rows, cols, C[rows, cols], al, be,
+                              transa=ta, transb=tb, k=n)
+        assert np.array_equal(got[rows, cols], want), (ta, tb)

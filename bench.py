@@ -714,7 +714,7 @@ def main() -> int:
     ap.add_argument("--extras", type=int, default=1,
                     help="Rgemm workloads: also measure the batched (LU, Cholesky) and served (LU) "
                          "workloads and the one-thread oracle, reported in the same line (0: skip)")
-    ap.add_argument("--extras-qps", type=float, default=150.0,
+    ap.add_argument("--extras-qps", type=float, default=200.0,
                     help="arrival rate of the served workload measured with --extras")
     ap.add_argument("--extras-single", type=int, default=100,
                     help="batched systems also solved one at a time with --extras")

@@ -184,6 +184,29 @@ int posit32_elementwise(void* stream, int op, int64_t n, const posit32_t* a,
 int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                   int32_t* ipiv, int32_t* info);
 /*
+ * posit32_getrf_group -- posit32_getrf on count <= P32_GROUP_MAX independent
+ *   square systems at once (the large systems of a serving batch): system i
+ *   is n[i] x n[i] at A[i] with leading dimension lda[i], its pivots go to
+ *   ipiv[i] and its status to info[i], exactly as posit32_getrf(stream,
+ *   n[i], nb, A[i], lda[i], ipiv[i], info[i]) would write them, bit for bit.
+ *   The systems advance panel by panel together: at each panel step the
+ *   panels of all systems still being factored run in one cooperative launch
+ *   (the workgroups split among them by remaining rows), and their
+ *   interchanges, U12 solves and trailing updates in one launch each, so the
+ *   per-column latency of the panels is shared.  n, A, lda, ipiv and info are
+ *   HOST arrays of count entries; the matrices, pivot vectors and info words
+ *   they point to are device memory and must not overlap.  Takes a
+ *   stream-ordered temporary of about 1 MB + 4 KB per system.  Errors: -2
+ *   count outside [0, P32_GROUP_MAX], -3 n NULL or some n[i] outside
+ *   [0, 2^24 - 2], -4 nb outside [1, 256], -5 A NULL, A[i] NULL with n[i] >
+ *   0, or two systems at one address, -6 lda NULL or lda[i] < max(1, n[i]),
+ *   -7 ipiv NULL or ipiv[i] NULL with n[i] > 0, -8 info NULL or info[i] NULL.
+ */
+#define P32_GROUP_MAX 16
+int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, posit32_t* const* A,
+                        const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
+
+/*
  * posit32_getrf_noalloc -- posit32_getrf (same arguments, validation, order
  *   of operations and result bits) for callers that cannot allocate device
  *   memory: code under stream capture by a harness that forbids hipMalloc,
@@ -336,7 +359,8 @@ int posit32_vbatched_default_tuning(int kind, posit32_vbatch_tuning* out);
  *    n <= cfg->batch_max_n / 2 through the batched kernels, and those with
  *    n <= cfg->batch_max_n too when at least four of them are in the batch
  *    (alone, such a system is faster through the single-matrix routines);
- *    the others through the single-matrix routines.  Host-to-device copies
+ *    the others through the single-matrix routines, the new LU systems among
+ *    them factored together as by posit32_getrf_group.  Host-to-device copies
  *    overlap the previous batch's computation.
  *  - Each system is factored and solved exactly as posit32_gesv_vbatched /
  *    posit32_posv_vbatched (or the single-matrix calls) with block size

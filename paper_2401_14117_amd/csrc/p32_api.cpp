@@ -77,6 +77,32 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
   return p32::launch_getrf((hipStream_t)stream, n, nb, A, lda, ipiv, info);
 }
 
+int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, posit32_t* const* A,
+                        const int64_t* lda, int32_t* const* ipiv, int32_t* const* info) {
+  if (count < 0 || count > P32_GROUP_MAX) return -2;
+  if (count == 0) return 0;
+  if (n == nullptr) return -3;
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 0 || n[i] > 0xFFFFFE) return -3;   // pivot rows are carried in 24 bits
+  if (nb < 1 || nb > 256) return -4;
+  if (A == nullptr) return -5;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 0 && A[i] == nullptr) return -5;
+  if (lda == nullptr) return -6;
+  for (int i = 0; i < count; ++i)
+    if (lda[i] < (n[i] > 1 ? n[i] : 1)) return -6;
+  if (ipiv == nullptr) return -7;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 0 && ipiv[i] == nullptr) return -7;
+  if (info == nullptr) return -8;
+  for (int i = 0; i < count; ++i)
+    if (info[i] == nullptr) return -8;
+  for (int i = 0; i < count; ++i)                  // systems must not share memory
+    for (int k = 0; k < i; ++k)
+      if (n[i] > 0 && n[k] > 0 && A[i] == A[k]) return -5;
+  return p32::launch_getrf_group((hipStream_t)stream, count, n, nb, A, lda, ipiv, info);
+}
+
 int posit32_getrf_noalloc(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                           int32_t* ipiv, int32_t* info) {
   if (n < 0) return -2;

@@ -115,6 +115,61 @@ static int pick_shape(int64_t m, int64_t n) {
   return 2;
 }
 
+// Several independent Rgemm problems (no transposes, 64 x 32 tiles) in one
+// launch: workgroup b takes tile b - tstart[s] of the problem s whose tile
+// range holds b.
+struct GemmGroup {
+  int count;
+  uint32_t alpha, beta;
+  unsigned tstart[kGemmGroupMax + 1];
+  int64_t m[kGemmGroupMax], n[kGemmGroupMax], k[kGemmGroupMax];
+  const uint32_t* A[kGemmGroupMax];
+  const uint32_t* B[kGemmGroupMax];
+  uint32_t* C[kGemmGroupMax];
+  int64_t lda[kGemmGroupMax], ldb[kGemmGroupMax], ldc[kGemmGroupMax];
+};
+
+__global__ void __launch_bounds__(NT, P32_GEMM_MIN_WAVES) gemm_group_kernel(GemmGroup g) {
+  __shared__ TileLds sm;
+  int s = 0;
+  while (s + 1 < g.count && blockIdx.x >= g.tstart[s + 1]) ++s;
+  int64_t i0, j0;
+  tile_origin(g.m[s], g.n[s], blockIdx.x - g.tstart[s], i0, j0);
+  gemm_tile<false, false, false, false>(g.m[s], g.n[s], g.k[s], g.A[s], g.lda[s], g.B[s], g.ldb[s], g.C[s],
+                                        g.ldc[s], g.alpha, g.beta, i0, j0, sm);
+}
+
+int launch_gemm_group(hipStream_t s, int count, const int64_t* m, const int64_t* n, const int64_t* k,
+                      const uint32_t* const* A, const int64_t* lda, const uint32_t* const* B,
+                      const int64_t* ldb, uint32_t* const* C, const int64_t* ldc, uint32_t alpha,
+                      uint32_t beta) {
+  if (count < 0 || count > kGemmGroupMax || alpha == 0u) return -1;
+  GemmGroup g{};
+  g.alpha = alpha;
+  g.beta = beta;
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    if (m[i] <= 0 || n[i] <= 0 || k[i] <= 0) continue;
+    const int c = g.count++;
+    g.tstart[c] = (unsigned)tiles;
+    g.m[c] = m[i];
+    g.n[c] = n[i];
+    g.k[c] = k[i];
+    g.A[c] = A[i];
+    g.B[c] = B[i];
+    g.C[c] = C[i];
+    g.lda[c] = lda[i];
+    g.ldb[c] = ldb[i];
+    g.ldc[c] = ldc[i];
+    tiles += ((m[i] + BM - 1) / BM) * ((n[i] + BN - 1) / BN);
+    if (tiles * NT >= ((int64_t)1 << 32)) return -4;
+  }
+  if (g.count == 0) return 0;
+  g.tstart[g.count] = (unsigned)tiles;
+  hipLaunchKernelGGL(gemm_group_kernel, dim3((unsigned)tiles), dim3(NT), 0, s, g);
+  return launch_status();
+}
+
 // alpha == 0 or k == 0: C = (beta == 0) ? 0 : beta*C
 __global__ void scale_c_kernel(int64_t m, int64_t n, uint32_t* __restrict__ C, int64_t ldc,
                                uint32_t beta, bool lower, const int32_t* __restrict__ skip) {

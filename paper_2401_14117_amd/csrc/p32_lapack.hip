@@ -133,21 +133,30 @@ __device__ __forceinline__ int64_t slot_row(unsigned long long v) {
 // between them.
 // Workspace: slot [2][G], crow [2][G][jb], rowc [2][jb], the row copies as
 // tagged words, every tag initially 0xFFFFFFFF (no column).
+// LDS of the panel factorisation besides the rows themselves
+struct PanelShared {
+  uint32_t urow[kMaxNB];
+  int2 ustg[kMaxNB];                              // urow staged as op(B) operands
+  unsigned long long red[2][kPanelThreads / 64];
+  lut_t lut[256];
+};
+
+// The panel factorisation as run by workgroup w of the G that share the
+// panel (tile: the LDS rows when LDS).
 template <bool LDS>
-__global__ void __launch_bounds__(kPanelThreads)
-lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int jb, int R,
-                unsigned long long* __restrict__ slot, unsigned long long* __restrict__ crow,
-                unsigned long long* __restrict__ rowc, int32_t* __restrict__ ipiv,
-                int32_t* __restrict__ info) {
-  __shared__ uint32_t tile[LDS ? kPanelLds : 1];
-  __shared__ uint32_t urow[kMaxNB];
-  __shared__ int2 ustg[kMaxNB];                   // urow staged as op(B) operands
-  __shared__ unsigned long long red[2][kPanelThreads / 64];
-  __shared__ lut_t lut[256];
+__device__ __forceinline__ void lu_panel_body(uint32_t* __restrict__ tile, PanelShared& sh,
+                                              uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j,
+                                              int jb, int R, const unsigned G, const unsigned w,
+                                              unsigned long long* __restrict__ slot,
+                                              unsigned long long* __restrict__ crow,
+                                              unsigned long long* __restrict__ rowc, int32_t* __restrict__ ipiv,
+                                              int32_t* __restrict__ info) {
+  auto& urow = sh.urow;
+  auto& ustg = sh.ustg;
+  auto& red = sh.red;
+  auto& lut = sh.lut;
 
   const int t = threadIdx.x;
-  const unsigned G = gridDim.x;
-  const unsigned w = blockIdx.x;
   const int64_t r0 = j + (int64_t)w * R;
   const int nr = (int)min((int64_t)R, n - r0);   // >= 1 by the host's choice of G
   uint32_t* T = LDS ? tile : A + r0 * lda + j;
@@ -318,10 +327,60 @@ lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int
     }
 }
 
+template <bool LDS>
+__global__ void __launch_bounds__(kPanelThreads)
+lu_panel_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int jb, int R,
+                unsigned long long* __restrict__ slot, unsigned long long* __restrict__ crow,
+                unsigned long long* __restrict__ rowc, int32_t* __restrict__ ipiv,
+                int32_t* __restrict__ info) {
+  __shared__ uint32_t tile[LDS ? kPanelLds : 1];
+  __shared__ PanelShared sh;
+  lu_panel_body<LDS>(tile, sh, A, lda, n, j, jb, R, gridDim.x, blockIdx.x, slot, crow, rowc, ipiv, info);
+}
+
+// ---- several systems at once ---------------------------------------------------
+// Up to kGroupMax independent LU factorisations advance panel by panel
+// together: the panels of all systems at one step in one cooperative launch
+// (the workgroups split among the systems, each system with its own exchange
+// slots), then one launch each for the interchanges, the U12 solves and the
+// trailing updates of every system.  Each system receives exactly the
+// operations of its single-matrix factorisation, in the same order.
+constexpr int kGroupMax = 16;
+
+struct PanelGroup {
+  int count;
+  int64_t j;
+  int gstart[kGroupMax + 1];                      // first workgroup of each system
+  int R[kGroupMax], jb[kGroupMax];
+  uint32_t* A[kGroupMax];
+  int64_t lda[kGroupMax], n[kGroupMax];
+  unsigned long long *slot[kGroupMax], *crow[kGroupMax], *rowc[kGroupMax];
+  int32_t *ipiv[kGroupMax], *info[kGroupMax];
+};
+
+__device__ __forceinline__ int group_of(const int* start, int count, unsigned b) {
+  int s = 0;
+  while (s + 1 < count && b >= (unsigned)start[s + 1]) ++s;
+  return s;
+}
+
+__global__ void __launch_bounds__(kPanelThreads) lu_panel_group_kernel(PanelGroup g) {
+  __shared__ uint32_t tile[kPanelLds];
+  __shared__ PanelShared sh;
+  const int s = group_of(g.gstart, g.count, blockIdx.x);
+  const unsigned G = (unsigned)(g.gstart[s + 1] - g.gstart[s]), w = blockIdx.x - (unsigned)g.gstart[s];
+  if ((int64_t)g.R[s] * g.jb[s] <= kPanelLds)
+    lu_panel_body<true>(tile, sh, g.A[s], g.lda[s], g.n[s], g.j, g.jb[s], g.R[s], G, w, g.slot[s], g.crow[s],
+                        g.rowc[s], g.ipiv[s], g.info[s]);
+  else
+    lu_panel_body<false>(tile, sh, g.A[s], g.lda[s], g.n[s], g.j, g.jb[s], g.R[s], G, w, g.slot[s],
+                         g.crow[s], g.rowc[s], g.ipiv[s], g.info[s]);
+}
+
 // apply the interchanges of panel [j, j+jb) to the columns outside it
-__global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb,
-                             const int32_t* __restrict__ ipiv) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void laswp_body(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j,
+                                           int64_t jb, const int32_t* __restrict__ ipiv, unsigned bx) {
+  int64_t q = (int64_t)bx * blockDim.x + threadIdx.x;
   if (q >= n - jb) return;
   if (q >= j) q += jb;                            // skip the panel's columns
   for (int64_t c = j; c < j + jb; ++c) {
@@ -334,6 +393,16 @@ __global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, i
   }
 }
 
+__global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb,
+                             const int32_t* __restrict__ ipiv) {
+  laswp_body(A, lda, n, j, jb, ipiv, blockIdx.x);
+}
+
+__global__ void laswp_group_kernel(PanelGroup g) {
+  const int s = blockIdx.y;
+  laswp_body(g.A[s], g.lda[s], g.n[s], g.j, g.jb[s], g.ipiv[s], blockIdx.x);
+}
+
 // U12 = L11^-1 A12 (L11 unit lower, jb x jb at A[j][j]); one workgroup per
 // column q of A12, thread r owns row j + r of it and keeps it decoded (window
 // form, plus a NaR flag) across the column steps.  Per column c in ascending
@@ -344,14 +413,20 @@ __global__ void laswp_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, i
 // coefficients ahead.
 constexpr int kTrsmPrefetch = 8;
 
-__global__ void __launch_bounds__(256)
-trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb) {
-  __shared__ int xc_nar[2];
-  __shared__ dec xc_d[2];
-  __shared__ lut_t lut[256];
+struct TrsmShared {
+  int xc_nar[2];
+  dec xc_d[2];
+  lut_t lut[256];
+};
+
+__device__ __forceinline__ void trsm_lu_body(TrsmShared& sh, uint32_t* __restrict__ A, int64_t lda, int64_t j,
+                                             int64_t jb, unsigned bx) {
+  auto& xc_nar = sh.xc_nar;
+  auto& xc_d = sh.xc_d;
+  auto& lut = sh.lut;
   const int t = threadIdx.x;
   lut[t] = make_lut_entry(t);
-  const int64_t q = j + jb + blockIdx.x;
+  const int64_t q = j + jb + bx;
   const bool mine = t < jb;
   const uint32_t x0 = mine ? A[(j + t) * lda + q] : 0u;
   bool xnar = x0 == kNaR;
@@ -389,6 +464,21 @@ trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int6
     for (int i = 0; i < kTrsmPrefetch; ++i) cur[i] = nxt[i];
   }
   if (mine) A[(j + t) * lda + q] = xnar ? kNaR : encode_win(unbias(acc));
+}
+
+__global__ void __launch_bounds__(256)
+trsm_lu_kernel(uint32_t* __restrict__ A, int64_t lda, int64_t n, int64_t j, int64_t jb) {
+  __shared__ TrsmShared sh;
+  trsm_lu_body(sh, A, lda, j, jb, blockIdx.x);
+}
+
+// column blockIdx.x of system blockIdx.y's A12 (systems with fewer columns
+// return at once, the whole workgroup together)
+__global__ void __launch_bounds__(256) trsm_lu_group_kernel(PanelGroup g) {
+  __shared__ TrsmShared sh;
+  const int s = blockIdx.y;
+  if ((int64_t)blockIdx.x >= g.n[s] - g.j - g.jb[s]) return;
+  trsm_lu_body(sh, g.A[s], g.lda[s], g.j, g.jb[s], blockIdx.x);
 }
 
 // ---- Cholesky --------------------------------------------------------------
@@ -872,6 +962,131 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
   hipError_t e = hipMallocAsync((void**)&ws, getrf_ws_bytes(gmax), s);
   if (e != hipSuccess) return -1000 - (int)e;
   rc = getrf_run(s, n, nb, A, lda, ipiv, info, ws, gmax, cus, per_cu_lds, per_cu_glb);
+  e = hipFreeAsync(ws, s);
+  if (rc != 0) return rc;
+  if (e != hipSuccess) return -1000 - (int)e;
+  return launch_status();
+}
+
+__global__ void fill_slots_kernel(unsigned long long* p, int count, unsigned long long v) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = v;
+}
+
+static_assert(kGetrfGroupMax == kGroupMax, "one system limit for the grouped LU");
+
+// Several LU factorisations advanced panel by panel together.  At panel
+// step j every system with n > j takes part: its panel gets a share of the
+// panel workgroups proportional to its remaining rows (at least one, at
+// least P32_PANEL_MIN_ROWS rows each), and its own exchange slots; the
+// interchanges, U12 solves and trailing updates of all systems then go in
+// one launch each.  The slots use an 8-bit column tag, and a system's slot
+// region moves as the shares change, so every slot is reset before each
+// panel step to a tag that neither of the step's first two columns has; the
+// row copies carry the full column number, which only grows.
+int launch_getrf_group(hipStream_t s, int count, const int64_t* n, int64_t nb, uint32_t* const* A,
+                       const int64_t* lda, int32_t* const* ipiv, int32_t* const* info) {
+  if (count < 0 || count > kGroupMax) return -1;
+  int64_t nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info[i]);
+    nmax = n[i] > nmax ? n[i] : nmax;
+  }
+  if (nmax == 0) return launch_status();
+  int cus = 0, per_cu_lds = 0, per_cu_glb = 0, per_cu_group = 0;
+  int64_t gmax = 0;
+  int rc = getrf_setup(kPanelThreads, &cus, &per_cu_lds, &per_cu_glb, &gmax);
+  if (rc != 0) return rc;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu_group, reinterpret_cast<const void*>(&lu_panel_group_kernel), kPanelThreads, 0);
+  if (e != hipSuccess) return -1000 - (int)e;
+  if (per_cu_group < 1) return -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+  if (gmax < count) return -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+
+  const size_t slot_bytes = (size_t)2 * gmax * sizeof(unsigned long long);
+  const size_t crow_bytes = (size_t)2 * gmax * kMaxNB * sizeof(unsigned long long);
+  const size_t rowc_bytes = (size_t)count * 2 * kMaxNB * sizeof(unsigned long long);
+  char* ws = nullptr;
+  e = hipMallocAsync((void**)&ws, slot_bytes + crow_bytes + rowc_bytes, s);
+  if (e != hipSuccess) return -1000 - (int)e;
+  unsigned long long* slot = reinterpret_cast<unsigned long long*>(ws);
+  unsigned long long* crow = reinterpret_cast<unsigned long long*>(ws + slot_bytes);
+  unsigned long long* rowc = reinterpret_cast<unsigned long long*>(ws + slot_bytes + crow_bytes);
+  const int64_t ws_words = (int64_t)((slot_bytes + crow_bytes + rowc_bytes) / sizeof(unsigned long long));
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((ws_words + 255) / 256)), dim3(256), 0, s, slot,
+                     ws_words, ~0ull);
+  rc = launch_status();
+  for (int64_t j = 0; j < nmax && rc == 0; j += nb) {
+    PanelGroup g{};
+    g.j = j;
+    int sys[kGroupMax];
+    int64_t rows_total = 0;
+    for (int i = 0; i < count; ++i)
+      if (n[i] > j) {
+        sys[g.count++] = i;
+        rows_total += n[i] - j;
+      }
+    const int64_t budget = gmax - g.count;          // one workgroup each, the rest by rows
+    int G = 0;
+    int64_t rest_max = 0, cols_max = 0;
+    for (int a = 0; a < g.count; ++a) {
+      const int i = sys[a];
+      const int64_t rows = n[i] - j;
+      int64_t Gs = 1 + budget * rows / rows_total;
+      int64_t R = (rows + Gs - 1) / Gs;
+      if (R < P32_PANEL_MIN_ROWS) R = P32_PANEL_MIN_ROWS;
+      Gs = (rows + R - 1) / R;
+      g.gstart[a] = G;
+      g.R[a] = (int)R;
+      g.jb[a] = (int)(nb < rows ? nb : rows);
+      g.A[a] = A[i];
+      g.lda[a] = lda[i];
+      g.n[a] = n[i];
+      g.slot[a] = slot + 2 * G;
+      g.crow[a] = crow + (size_t)2 * G * kMaxNB;
+      g.rowc[a] = rowc + (size_t)i * 2 * kMaxNB;
+      g.ipiv[a] = ipiv[i];
+      g.info[a] = info[i];
+      G += (int)Gs;
+      rest_max = rows - g.jb[a] > rest_max ? rows - g.jb[a] : rest_max;
+      cols_max = n[i] - g.jb[a] > cols_max ? n[i] - g.jb[a] : cols_max;
+    }
+    g.gstart[g.count] = G;
+    if (G > per_cu_group * (int64_t)cus || G > gmax) {
+      rc = -1000 - (int)hipErrorCooperativeLaunchTooLarge;
+      break;
+    }
+    hipLaunchKernelGGL(fill_slots_kernel, dim3(1), dim3(256), 0, s, slot, 2 * G,
+                       (unsigned long long)((j + 2) & 0xFF));
+    void* args[] = {&g};
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&lu_panel_group_kernel), dim3((unsigned)G),
+                                   dim3(kPanelThreads), args, 0, s);
+    if (e != hipSuccess) {
+      rc = -1000 - (int)e;
+      break;
+    }
+    if (cols_max > 0)
+      hipLaunchKernelGGL(laswp_group_kernel, dim3((unsigned)((cols_max + 255) / 256), (unsigned)g.count),
+                         dim3(256), 0, s, g);
+    if (rest_max > 0) {
+      hipLaunchKernelGGL(trsm_lu_group_kernel, dim3((unsigned)rest_max, (unsigned)g.count), dim3(256), 0, s,
+                         g);
+      int64_t mm[kGroupMax], kk[kGroupMax], ld[kGroupMax];
+      const uint32_t* Ap[kGroupMax];
+      const uint32_t* Bp[kGroupMax];
+      uint32_t* Cp[kGroupMax];
+      for (int a = 0; a < g.count; ++a) {
+        const int64_t jb = g.jb[a], ldA = g.lda[a];
+        mm[a] = g.n[a] - j - jb;
+        kk[a] = jb;
+        ld[a] = ldA;
+        Ap[a] = g.A[a] + (j + jb) * ldA + j;
+        Bp[a] = g.A[a] + j * ldA + j + jb;
+        Cp[a] = g.A[a] + (j + jb) * ldA + j + jb;
+      }
+      rc = launch_gemm_group(s, g.count, mm, mm, kk, Ap, ld, Bp, ld, Cp, ld, kMinusOne, kOne);
+    }
+    if (rc == 0) rc = launch_status();
+  }
   e = hipFreeAsync(ws, s);
   if (rc != 0) return rc;
   if (e != hipSuccess) return -1000 - (int)e;

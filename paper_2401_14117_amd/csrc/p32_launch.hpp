@@ -20,6 +20,13 @@ int launch_gemm(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, 
 int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
                    const uint32_t* A, int64_t lda, const uint32_t* B, int64_t ldb, uint32_t beta,
                    uint32_t* C, int64_t ldc, bool lower, const int32_t* skip);
+// count <= kGemmGroupMax independent problems C_s = alpha A_s B_s + beta C_s
+// (no transposes, alpha != 0) in one launch; host arrays, empty problems skipped
+constexpr int kGemmGroupMax = 16;
+int launch_gemm_group(hipStream_t s, int count, const int64_t* m, const int64_t* n, const int64_t* k,
+                      const uint32_t* const* A, const int64_t* lda, const uint32_t* const* B,
+                      const int64_t* ldb, uint32_t* const* C, const int64_t* ldc, uint32_t alpha,
+                      uint32_t beta);
 // C_ij = rnd(C_ij - rnd(A_ip * op(B)_pj)) for p = 0 .. k-1 in order (A not
 // transposed; op(B) = B or B^T by tb; lower: only row >= column of C)
 int launch_fms_chain(hipStream_t s, int tb, int64_t m, int64_t n, int64_t k, const uint32_t* A,
@@ -32,6 +39,12 @@ int launch_elementwise(hipStream_t s, int op, int64_t n, const uint32_t* a, cons
 
 int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                  int32_t* info);
+// count <= kGetrfGroupMax independent LU factorisations advanced together
+// (host arrays of device pointers); each system's results are those of
+// launch_getrf on it
+constexpr int kGetrfGroupMax = P32_GROUP_MAX;
+int launch_getrf_group(hipStream_t s, int count, const int64_t* n, int64_t nb, uint32_t* const* A,
+                       const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
 // getrf on the library's file-scope device scratch (no allocation)
 int launch_getrf_noalloc(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                          int32_t* info);

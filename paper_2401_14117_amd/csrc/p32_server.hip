@@ -16,7 +16,11 @@
 //     systems with n <= batch_max_n / 2 go through the batched kernels (one
 //     launch per kind), and so do those with n <= batch_max_n when at least
 //     kMidShare of them are in the batch; the others go through the
-//     single-matrix routines;
+//     single-matrix routines, except that the new LU systems among them are
+//     factored together (launch_getrf_group: their panels in one cooperative
+//     launch per panel step, their trailing updates in one launch), so large
+//     systems in one batch share the device instead of queueing behind each
+//     other;
 //   * overlap: a batch's host-to-device copies run on a copy stream while the
 //     previous batch computes on the compute stream; results come back on the
 //     compute stream and are copied out when its event completes;
@@ -362,6 +366,26 @@ int start_batch(posit32_queue* q, Slot& s) {
                        (int32_t)large.size());
     rc = p32::launch_status();
   }
+  // the new LU systems among them are factored together, up to
+  // kGetrfGroupMax at a time (their panels share the per-column latency)
+  std::vector<Req*> lu_new;
+  for (Req* r : large)
+    if (r->kind == 0 && !r->factor_in) lu_new.push_back(r);
+  for (size_t g0 = 0; g0 < lu_new.size() && !rc; g0 += p32::kGetrfGroupMax) {
+    const int c = (int)std::min(lu_new.size() - g0, (size_t)p32::kGetrfGroupMax);
+    int64_t n[p32::kGetrfGroupMax], lda[p32::kGetrfGroupMax];
+    uint32_t* A[p32::kGetrfGroupMax];
+    int32_t* ipiv[p32::kGetrfGroupMax];
+    int32_t* info[p32::kGetrfGroupMax];
+    for (int i = 0; i < c; ++i) {
+      Req* r = lu_new[g0 + i];
+      n[i] = lda[i] = r->n;
+      A[i] = (uint32_t*)(pool + r->fac_off);
+      ipiv[i] = (int32_t*)(pool + r->fac_off + round_up((size_t)r->n * r->n * 4));
+      info[i] = dinfo + sub + (int32_t)(std::find(large.begin(), large.end(), r) - large.begin());
+    }
+    rc = p32::launch_getrf_group(q->compute, c, n, q->cfg.nb, A, lda, ipiv, info);
+  }
   for (Req* r : large) {
     if (rc) break;
     uint32_t* A = (uint32_t*)(pool + r->fac_off);
@@ -370,7 +394,6 @@ int start_batch(posit32_queue* q, Slot& s) {
     int32_t* info = dinfo + sub;
     r->info = sub++;
     if (r->kind == 0) {
-      if (!r->factor_in) rc = p32::launch_getrf(q->compute, r->n, q->cfg.nb, A, r->n, ipiv, info);
       if (!rc) rc = p32::launch_getrs(q->compute, 0, r->n, r->nrhs, A, r->n, ipiv, B, r->nrhs);
     } else {
       if (!r->factor_in) rc = p32::launch_potrf(q->compute, 0, r->n, q->cfg.nb, A, r->n, info);

@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
     L.posit32_getrf.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     L.posit32_getrf_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.posit32_getrf_group.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp]
+    L.posit32_getrf_group.restype = i32
     L.posit32_getrf_noalloc.restype = i32
     L.posit32_getrs.argtypes = [vp, i32, i64, i64, vp, i64, vp, vp, i64]
     L.posit32_potrf.argtypes = [vp, i32, i64, i64, vp, i64, vp]
@@ -324,6 +326,26 @@ def getrf(A: torch.Tensor, nb: int = 256, stream=None):
     _check(lib().posit32_getrf(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(ipiv), _ptr(info)),
            "posit32_getrf")
     return A, ipiv[:n], info
+
+
+GROUP_MAX = 16
+
+
+def getrf_group(As, nb: int = 256, stream=None):
+    """In place LU of up to GROUP_MAX independent square matrices advanced
+    together (posit32_getrf_group); returns [(A, ipiv, info)] as getrf."""
+    if len(As) > GROUP_MAX:
+        raise ValueError(f"at most {GROUP_MAX} systems per group")
+    count = len(As)
+    ns = (ctypes.c_int64 * max(count, 1))(*[_square(A) for A in As])
+    ldas = (ctypes.c_int64 * max(count, 1))(*[_ld(A) for A in As])
+    ipivs = [torch.empty(max(A.shape[0], 1), dtype=torch.int32, device=A.device) for A in As]
+    infos = [torch.empty(1, dtype=torch.int32, device=A.device) for A in As]
+    Ap = (ctypes.c_void_p * max(count, 1))(*[A.data_ptr() for A in As])
+    Pp = (ctypes.c_void_p * max(count, 1))(*[p.data_ptr() for p in ipivs])
+    Ip = (ctypes.c_void_p * max(count, 1))(*[i.data_ptr() for i in infos])
+    _check(lib().posit32_getrf_group(_stream(stream), count, ns, nb, Ap, ldas, Pp, Ip), "posit32_getrf_group")
+    return [(A, p[:A.shape[0]], i) for A, p, i in zip(As, ipivs, infos)]
 
 
 def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, stream=None,

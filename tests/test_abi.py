@@ -90,6 +90,20 @@ def test_factorisation_argument_errors(L):
     assert L.posit32_getrf_noalloc(None, 4, 64, 8, 4, None, 8) == -6
     assert L.posit32_getrf_noalloc(None, 4, 64, 8, 4, 8, None) == -7
     assert L.posit32_getrf_noalloc(None, 1 << 24, 64, 8, 1 << 24, 8, 8) == -2
+    # getrf_group(stream, count, n[], nb, A[], lda[], ipiv[], info[]) with host arrays
+    I64x2, Px2 = ctypes.c_int64 * 2, ctypes.c_void_p * 2
+    n2, ld2, p2 = I64x2(4, 3), I64x2(4, 3), Px2(8, 16)
+    assert L.posit32_getrf_group(None, 17, n2, 64, p2, ld2, p2, p2) == -2
+    assert L.posit32_getrf_group(None, -1, n2, 64, p2, ld2, p2, p2) == -2
+    assert L.posit32_getrf_group(None, 0, None, 64, None, None, None, None) == 0
+    assert L.posit32_getrf_group(None, 2, None, 64, p2, ld2, p2, p2) == -3
+    assert L.posit32_getrf_group(None, 2, I64x2(4, -1), 64, p2, ld2, p2, p2) == -3
+    assert L.posit32_getrf_group(None, 2, n2, 0, p2, ld2, p2, p2) == -4
+    assert L.posit32_getrf_group(None, 2, n2, 64, Px2(8, None), ld2, p2, p2) == -5
+    assert L.posit32_getrf_group(None, 2, n2, 64, Px2(8, 8), ld2, p2, p2) == -5     # shared matrix
+    assert L.posit32_getrf_group(None, 2, n2, 64, p2, I64x2(4, 2), p2, p2) == -6
+    assert L.posit32_getrf_group(None, 2, n2, 64, p2, ld2, None, p2) == -7
+    assert L.posit32_getrf_group(None, 2, n2, 64, p2, ld2, p2, Px2(8, None)) == -8
     # getrs(stream, op, n, nrhs, LU, lda, ipiv, B, ldb)
     assert L.posit32_getrs(None, 2, 4, 1, 8, 4, 8, 8, 1) == -2
     assert L.posit32_getrs(None, -1, 4, 1, 8, 4, 8, 8, 1) == -2

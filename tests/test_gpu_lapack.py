@@ -103,6 +103,44 @@ def test_potrf_not_positive_definite(P, bad):
     assert np.array_equal(gL, L), _diff(gL, L)
 
 
+def test_getrf_group_parity(P):
+    """posit32_getrf_group: eight systems of different sizes (one with a zero
+    column, one with a NaR) factored together, each equal to the oracle's
+    factorisation bit for bit; then the same with nb = 64."""
+    import torch
+    sizes = [768, 1, 300, 5, 520, 64, 257, 130]
+    rng = np.random.default_rng(77)
+    mats = [p32(rng.uniform(-1, 1, (k, k)) * 2.0 ** rng.integers(-3, 4, (k, k))) for k in sizes]
+    mats[2][:, 40] = 0                                 # info = 41
+    mats[4][500, 7] = NAR
+    for nb in (256, 64):
+        devs = [to_dev(a) for a in mats]
+        out = P.getrf_group(devs, nb)
+        torch.cuda.synchronize()
+        for a, (Ad, ipiv, info) in zip(mats, out):
+            LU, piv, inf = O.getrf(a, nb)
+            assert int(info.item()) == inf
+            assert np.array_equal(ipiv.cpu().numpy(), piv)
+            assert np.array_equal(from_dev(Ad), LU), _diff(from_dev(Ad), LU)
+
+
+def test_getrf_group_matches_single_large(P):
+    """A group of the serving workload's larger sizes (600..2048): every
+    system bit-identical to posit32_getrf on it alone."""
+    import torch
+    sizes = [2048, 600, 1500, 1024, 777, 1999, 640, 1100, 900, 1300]
+    rng = np.random.default_rng(78)
+    mats = [P.from_f64(torch.from_numpy(rng.uniform(-1, 1, (k, k))).cuda()) for k in sizes]
+    group = P.getrf_group([m.clone() for m in mats], 256)
+    for m, (Ag, pg, ig) in zip(mats, group):
+        As = m.clone()
+        _, ps, is_ = P.getrf(As, 256)
+        torch.cuda.synchronize()
+        assert int(ig.item()) == int(is_.item()) == 0
+        assert torch.equal(pg, ps)
+        assert torch.equal(Ag, As)
+
+
 def test_exact_recovery_on_gpu(P):
     """Dyadic L*U with pivot-preserving |L| < 1, rows shuffled: the GPU
     returns the exact factors (closed form, independent of the oracle)."""

@@ -205,3 +205,37 @@ def test_queue_failed_factorisation(P):
     assert outs[1]["info"] == O.potrf(N, 256)[1] > 0 and outs[1]["factor"] == 0
     assert outs[2]["info"] == 0 and np.array_equal(outs[2]["X"], _alone(P, 0, good, B)[0])
     assert st["resident_factors"] == 0
+
+
+def test_queue_large_lu_burst_factored_together(P):
+    """A burst of large LU systems (600..2048, one singular) submitted at
+    once: the queue factors the new ones of a batch together (grouped
+    panels and trailing updates); every solution equals the system solved
+    alone, and the oracle's for two of them."""
+    rng = np.random.default_rng(31)
+    sizes = [2048, 600, 1500, 700, 1024, 1999, 640, 768, 1100, 900, 1300, 650, 1800, 610, 1200, 1600, 800,
+             620]
+    reqs = []
+    for i, n in enumerate(sizes):
+        A = _lu(rng, n)
+        if i == 3:
+            A[:, 10] = 0                                # singular: info = 11, not solved
+        B = p32(rng.uniform(-1, 1, (n, int(rng.integers(1, 5)))))
+        reqs.append((A, B))
+    q = P.Queue(device_bytes=1 << 30, max_batch=64, nb=256, batch_max_n=512)
+    tickets = [q.submit(0, B, A) for A, B in reqs]
+    outs = [q.wait(t, 300.0) for t in tickets]
+    st = q.stats()
+    q.close()
+    assert st["batches"] < len(sizes)                   # several systems shared a batch
+    for i, ((A, B), out) in enumerate(zip(reqs, outs)):
+        assert out is not None and out["status"] == 0
+        X, info = _alone(P, 0, A, B)
+        assert out["info"] == info == (11 if i == 3 else 0)
+        if info == 0:
+            assert np.array_equal(out["X"], X), i
+        else:
+            assert np.array_equal(out["X"], B)           # a failed factorisation is not solved
+        if sizes[i] in (600, 768):
+            LU, ipiv, _ = O.getrf(A, 256)
+            assert np.array_equal(out["X"], O.getrs(LU, ipiv, B)), i

@@ -66,7 +66,10 @@ constexpr int kUnroll = P32_BATCH_UNROLL;   // k-steps unrolled in the tile rout
 constexpr uint32_t kMinus1 = 0xC0000000u;
 
 struct Shared {
-  TileLds tile;
+  union {
+    TileLdsT<BigTile> big;
+    TileLdsT<ThinTile> thin;
+  } tile;
   unsigned long long red[kBT / 64];
   uint32_t urow[kMaxSub];
   dec udec[kMaxSub];
@@ -88,16 +91,46 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
   return b;
 }
 
-// every 64 x 32 tile of an m x n region through the tile routine
+// f(r, q) for every r < rows, q < w, thread t taking the flat indices
+// t, t + kBT, ... (r = index / w, q = index % w) with the quotient and
+// remainder advanced incrementally: two divisions per call instead of one
+// per element.
+template <class F>
+__device__ __forceinline__ void for_each_rq(int64_t rows, int64_t w, F f) {
+  if (rows <= 0 || w <= 0) return;
+  const int64_t t = threadIdx.x;
+  const int64_t step_r = kBT / w, step_q = kBT % w;
+  int64_t r = t / w, q = t % w;
+  while (r < rows) {
+    f(r, q);
+    r += step_r;
+    q += step_q;
+    if (q >= w) {
+      q -= w;
+      ++r;
+    }
+  }
+}
+
+// every tile of an m x n region through the tile routine: 64 x 32 tiles,
+// or 64 x 16 when the region is at most 16 columns wide (the right-hand
+// sides of a solve), so that narrow regions are not padded to 32 columns
 template <bool TA, bool TB, bool LOWER, bool CHAIN, bool REVK>
 __device__ __forceinline__ void tiles(int64_t m, int64_t n, int64_t k, const uint32_t* A, int64_t lda,
                                       const uint32_t* B, int64_t ldb, uint32_t* C, int64_t ldc,
                                       uint32_t alpha, uint32_t beta, Shared& sh) {
   if (m <= 0 || n <= 0 || k <= 0) return;
-  const int64_t nr = (m + BM - 1) / BM, nc = (n + BN - 1) / BN;
-  for (int64_t t = 0; t < nr * nc; ++t)
-    gemm_tile<TA, TB, LOWER, CHAIN, REVK, kUnroll>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, (t / nc) * BM,
-                                          (t % nc) * BN, sh.tile);
+  if (!LOWER && n <= ThinTile::BN) {
+    const int64_t nr = (m + ThinTile::BM - 1) / ThinTile::BM;
+    for (int64_t t = 0; t < nr; ++t)
+      gemm_tile<TA, TB, LOWER, CHAIN, REVK, kUnroll, ThinTile>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta,
+                                                               t * ThinTile::BM, 0, sh.tile.thin);
+  } else {
+    const int64_t nr = (m + BM - 1) / BM, nc = (n + BN - 1) / BN;
+    for (int64_t t = 0; t < nr * nc; ++t)
+      gemm_tile<TA, TB, LOWER, CHAIN, REVK, kUnroll>(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta,
+                                                     (t / nc) * BM, (t % nc) * BN, sh.tile.big);
+  }
   __syncthreads();
 }
 
@@ -142,15 +175,12 @@ __device__ __forceinline__ void lu_subpanel(uint32_t* A, int64_t lda, int64_t n,
       for (int64_t i = c + 1 + t; i < n; i += kBT) A[i * lda + c] = p_div_by(A[i * lda + c], pd);
     }
     __syncthreads();
-    const int64_t cnt = (n - c - 1) * wq;
-    for (int64_t idx = t; idx < cnt; idx += kBT) {
-      const int64_t di = idx / wq;
-      const int q = (int)(idx - di * wq);
+    for_each_rq(n - c - 1, wq, [&](int64_t di, int64_t q) {
       const int64_t i = c + 1 + di;
       const uint32_t l = A[i * lda + c];
       uint32_t& x = A[i * lda + c + 1 + q];
       x = p_fms_pre(x, l, decode(l), sh.urow[q], sh.udec[q]);
-    }
+    });
     __syncthreads();
   }
 }
@@ -181,14 +211,11 @@ __device__ __forceinline__ void lu_trsm_rows(uint32_t* A, int64_t lda, int64_t c
   if (nq <= 0) return;
   for (int cl = 0; cl + 1 < w; ++cl) {
     const int64_t c = c0 + cl;
-    const int rows = w - cl - 1;
-    const int64_t cnt = rows * nq;
-    for (int64_t idx = threadIdx.x; idx < cnt; idx += kBT) {
-      const int64_t dr = idx / nq;
-      const int64_t q = q0 + (idx - dr * nq);
+    for_each_rq(w - cl - 1, nq, [&](int64_t dr, int64_t dq) {
+      const int64_t q = q0 + dq;
       const int64_t r = c + 1 + dr;
       A[r * lda + q] = p_fms(A[r * lda + q], A[r * lda + c], A[c * lda + q]);
-    }
+    });
     __syncthreads();
   }
 }
@@ -245,12 +272,10 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
     const int w = (int)(sub < n - c0 ? sub : n - c0);
     for (int cl = 0; cl + 1 < w; ++cl) {
       const int64_t c = c0 + cl;
-      const int64_t cnt = (w - cl - 1) * nrhs;
-      for (int64_t idx = t; idx < cnt; idx += kBT) {
-        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+      for_each_rq(w - cl - 1, nrhs, [&](int64_t dr, int64_t q) {
         const int64_t r = c + 1 + dr;
         B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
-      }
+      });
       __syncthreads();
     }
     const int64_t r1 = c0 + w;
@@ -263,12 +288,10 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
       const divisor dv = make_divisor(LU[c * lda + c]);
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
-      const int64_t cnt = (c - c0) * nrhs;
-      for (int64_t idx = t; idx < cnt; idx += kBT) {
-        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+      for_each_rq(c - c0, nrhs, [&](int64_t dr, int64_t q) {
         const int64_t r = c0 + dr;
         B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
-      }
+      });
       __syncthreads();
     }
     tiles<false, false, false, true, true>(c0, nrhs, c1 - c0, LU + c0, lda, B + c0 * ldb, ldb, B, ldb, 0u,
@@ -296,13 +319,12 @@ __device__ __forceinline__ int64_t chol_subblock(uint32_t* A, int64_t lda, int64
     const int rows = w - cl - 1;
     if (t < rows) A[(c + 1 + t) * lda + c] = p_div_by(A[(c + 1 + t) * lda + c], make_divisor(d));
     __syncthreads();
-    for (int idx = t; idx < rows * rows; idx += kBT) {
-      const int a = idx / rows, b = idx - a * rows;  // element (c+1+a, c+1+b), b <= a
+    for_each_rq(rows, rows, [&](int64_t a, int64_t b) {   // element (c+1+a, c+1+b), b <= a
       if (b <= a) {
         const int64_t i = c + 1 + a, q = c + 1 + b;
         A[i * lda + q] = p_fms(A[i * lda + q], A[i * lda + c], A[q * lda + c]);
       }
-    }
+    });
     __syncthreads();
   }
   return -1;
@@ -323,14 +345,11 @@ __device__ __forceinline__ void chol_trsm_rows(uint32_t* A, int64_t lda, int64_t
     const divisor dv = make_divisor(sh.diag[cl]);
     for (int64_t r = r0 + t; r < r1; r += kBT) A[r * lda + c] = p_div_by(A[r * lda + c], dv);
     __syncthreads();
-    const int wq = w - cl - 1;
-    const int64_t cnt = nr * wq;
-    for (int64_t idx = t; idx < cnt; idx += kBT) {
-      const int64_t dr = idx / wq;
-      const int64_t q = c + 1 + (idx - dr * wq);
+    for_each_rq(nr, w - cl - 1, [&](int64_t dr, int64_t dq) {
+      const int64_t q = c + 1 + dq;
       const int64_t r = r0 + dr;
       A[r * lda + q] = p_fms(A[r * lda + q], A[r * lda + c], A[q * lda + c]);
-    }
+    });
     __syncthreads();
   }
 }
@@ -378,12 +397,10 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
       const divisor dv = make_divisor(L[c * lda + c]);
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
-      const int64_t cnt = (w - cl - 1) * nrhs;
-      for (int64_t idx = t; idx < cnt; idx += kBT) {
-        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+      for_each_rq(w - cl - 1, nrhs, [&](int64_t dr, int64_t q) {
         const int64_t r = c + 1 + dr;
         B[r * ldb + q] = p_fms(B[r * ldb + q], L[r * lda + c], B[c * ldb + q]);
-      }
+      });
       __syncthreads();
     }
     const int64_t r1 = c0 + w;
@@ -396,12 +413,10 @@ __device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64
       const divisor dv = make_divisor(L[c * lda + c]);
       for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
       __syncthreads();
-      const int64_t cnt = (c - c0) * nrhs;
-      for (int64_t idx = t; idx < cnt; idx += kBT) {
-        const int64_t dr = idx / nrhs, q = idx - dr * nrhs;
+      for_each_rq(c - c0, nrhs, [&](int64_t dr, int64_t q) {
         const int64_t r = c0 + dr;
         B[r * ldb + q] = p_fms(B[r * ldb + q], L[c * lda + r], B[c * ldb + q]);
-      }
+      });
       __syncthreads();
     }
     // rows above the block: coefficient L[c][r] = op(A)(r, c) with op = transpose

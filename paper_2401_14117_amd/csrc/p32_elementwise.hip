@@ -54,6 +54,17 @@ __global__ void to_f64_kernel(int64_t n, const uint32_t* __restrict__ p, double*
   }
 }
 
+// maxpos (big) or minpos with the given sign
+__device__ __forceinline__ uint32_t saturated(bool neg, bool big) {
+  const uint32_t p = big ? 0x7FFFFFFFu : 1u;
+  return neg ? 0u - p : p;
+}
+
+// Sums and products that saturate are clamps, decided from the operands
+// alone (a decoded value lies in [2^sc, 2^(sc+1))): a product at or beyond
+// maxpos = 2^120 gives maxpos, one below minpos = 2^-120 gives minpos, and a
+// sum of two same-signed values of which one is maxpos gives maxpos.
+// Everything else takes the window-form fast path or the exact routines.
 __global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict__ a,
                                    const uint32_t* __restrict__ b, uint32_t* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -66,12 +77,26 @@ __global__ void elementwise_kernel(int op, int64_t n, const uint32_t* __restrict
       case 0:
       case 1: {
         const uint32_t yy = op == 1 ? 0u - y : y;
-        r = (xn || yn) ? kNaR : encode_win(add_win(win_of(x), win_of(yy)));
+        if (xn || yn) {
+          r = kNaR;
+        } else {
+          const bool same = x != 0u && yy != 0u && ((int32_t)x < 0) == ((int32_t)yy < 0);
+          if (same && (x == 0x7FFFFFFFu || x == 0x80000001u || yy == 0x7FFFFFFFu || yy == 0x80000001u))
+            r = saturated((int32_t)x < 0, true);
+          else
+            r = encode_win(add_win(win_of(x), win_of(yy)));
+        }
         break;
       }
-      case 2:
-        r = (xn || yn) ? kNaR : encode_win(mul_win(decode(x), decode(y)));
+      case 2: {
+        const dec dx = decode(x), dy = decode(y);
+        const int s2 = dx.sc + dy.sc;
+        if (xn || yn) r = kNaR;
+        else if (dx.s == 0 || dy.s == 0) r = 0u;
+        else if (s2 >= 120 || s2 <= -122) r = saturated((dx.s < 0) != (dy.s < 0), s2 >= 120);
+        else r = encode_win(mul_win(dx, dy));
         break;
+      }
       case 3: {
         const dec dx = decode(x), dy = decode(y);
         if (xn || yn || dy.s == 0) r = kNaR;         // x / 0 = NaR

@@ -51,6 +51,9 @@ using BigTile = TileShape<P32_GEMM_TM, P32_GEMM_TN, 16, 16, false>;
 // every compute unit several big tiles
 using MidTile = TileShape<2, 2, 16, 16, true>;
 using SmallTile = TileShape<1, 1, 8, 8, true>;
+// 64 x 16 per 256 threads: updates of at most 16 columns (the right-hand
+// sides of the batched solves, narrow panel remainders)
+using ThinTile = TileShape<4, 1, 16, 16, false>;
 
 constexpr int TM = BigTile::TM, TN = BigTile::TN, NT = BigTile::NT, BK = BigTile::BK;
 constexpr int BM = BigTile::BM, BN = BigTile::BN;

@@ -80,11 +80,11 @@ def summarize(args) -> None:
         "",
         "```",
         f"rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace -o trace -- "
-        f"python3 $REPO/bench.py --workload {args.workload} --steps 2 --warmup 1 --cpu-budget 0",
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 2 --warmup 1 --cpu-budget 0 --extras 0",
         f"rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/fetch -o fetch -- "
-        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0 --extras 0",
         f"rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/write -o write -- "
-        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0",
+        f"python3 $REPO/bench.py --workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0 --extras 0",
         "rocprofv3 --pmc FETCH_SIZE --kernel-trace --output-format csv -d $OUT/copyf -o copyf -- "
         "python3 $REPO/bench.py --copy-calibration",
         "rocprofv3 --pmc WRITE_SIZE --kernel-trace --output-format csv -d $OUT/copyw -o copyw -- "
@@ -148,16 +148,18 @@ def valu_table(args) -> None:
     name = next(k for k in stats if args.kernel in k)
     avg_ns = stats[name][1]
     m, n, k = args.mnk
-    madds = float(m) * n * k
+    madds = float(args.madds) if args.madds else float(m) * n * k
     ctr = {c: counter_per_dispatch(args.pmc, c, args.kernel) for c in args.counters}
     cycles = avg_ns * 1e-9 * args.clock_ghz * 1e9
-    lines = [f"# rocprofv3: VALU utilisation of the Posit(32,2) Rgemm kernel, {args.workload}", "",
+    bench_args = args.bench_args or f"--workload {args.workload} --steps 1 --warmup 0 --cpu-budget 0 --extras 0"
+    lines = [f"# rocprofv3: VALU utilisation of the {args.what}, {args.workload}", "",
              f"Kernel: `{name}`", f"Kernel source hash: {args.kernel_hash}.", "",
              "Commands (" + WHERE + "):", "", "```",
              f"rocprofv3 --pmc {' '.join(args.counters)} --kernel-trace --output-format csv "
-             f"-d $OUT/valu -o valu -- python3 $REPO/bench.py --workload {args.workload} "
-             "--steps 1 --warmup 0 --cpu-budget 0",
-             "(kernel duration from the --kernel-trace --stats run of the Rgemm summary)", "```", "",
+             f"-d $OUT/valu -o valu -- python3 $REPO/bench.py {bench_args}",
+             f"(kernel duration from the --kernel-trace --stats run: {args.trace_note})", "```", "",
+             f"Multiply-adds per dispatch: {madds:.4g}" + (f" ({args.madds_note})" if args.madds_note else "") + ".",
+             "",
              "| counter (per dispatch, summed over the chip) | value |", "|---|---|"]
     for c in args.counters:
         lines.append(f"| {c} | {ctr[c]:.4g} |")
@@ -197,6 +199,11 @@ def main() -> None:
         ap.add_argument("--clock-ghz", type=float, default=2.4)
         ap.add_argument("--kernel-hash", required=True)
         ap.add_argument("--out", required=True)
+        ap.add_argument("--what", default="Posit(32,2) Rgemm kernel")
+        ap.add_argument("--madds", type=float, default=0.0, help="multiply-adds per dispatch (default m n k)")
+        ap.add_argument("--madds-note", default="")
+        ap.add_argument("--bench-args", default="")
+        ap.add_argument("--trace-note", default="the Rgemm summary")
         valu_table(ap.parse_args())
         return
     if len(sys.argv) > 1 and sys.argv[1] == "kernels":

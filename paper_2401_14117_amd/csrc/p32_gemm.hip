@@ -99,7 +99,9 @@ static int64_t tile_count(int64_t m, int64_t n) {
 
 // Tile shape of a plain Rgemm launch: 64 x 32 tiles while they give every
 // compute unit at least four, else 32 x 32 tiles while those give every
-// compute unit at least two, else 8 x 8 tiles.  0 big, 1 mid, 2 small.
+// compute unit at least two, else 8 x 8 tiles -- with the latency-bound
+// checked k-steps when there are fewer than two of those per compute unit.
+// 0 big, 1 mid, 2 small, 3 tiny.
 static int pick_shape(int64_t m, int64_t n) {
   static int cus = 0;
   if (cus == 0) {
@@ -112,7 +114,8 @@ static int pick_shape(int64_t m, int64_t n) {
   }
   if (tile_count<BigTile>(m, n) >= 4 * (int64_t)cus) return 0;
   if (tile_count<MidTile>(m, n) >= 2 * (int64_t)cus) return 1;
-  return 2;
+  if (tile_count<SmallTile>(m, n) >= 2 * (int64_t)cus) return 2;
+  return 3;
 }
 
 // Several independent Rgemm problems (no transposes, 64 x 32 tiles) in one
@@ -208,12 +211,15 @@ int launch_gemm_ex(hipStream_t s, int ta, int tb, int64_t m, int64_t n, int64_t 
   if (shape != 0) {
     const int64_t t = shape == 1 ? tile_count<MidTile>(m, n) : tile_count<SmallTile>(m, n);
     const int nt = shape == 1 ? MidTile::NT : SmallTile::NT;
+    static_assert(TinyTile::BM == SmallTile::BM && TinyTile::BN == SmallTile::BN, "same tiling");
     if (t * nt >= ((int64_t)1 << 32)) return -4;
 #define P32_LAUNCH_S(TA_, TB_, S_) \
     hipLaunchKernelGGL((gemm_shape_kernel<TA_, TB_, S_>), dim3((unsigned)t), dim3(S_::NT), 0, s, m, n, k, A, \
                        lda, B, ldb, C, ldc, alpha, beta)
 #define P32_LAUNCH_T(TA_, TB_) \
-    if (shape == 1) P32_LAUNCH_S(TA_, TB_, MidTile); else P32_LAUNCH_S(TA_, TB_, SmallTile)
+    if (shape == 1) P32_LAUNCH_S(TA_, TB_, MidTile); \
+    else if (shape == 2) P32_LAUNCH_S(TA_, TB_, SmallTile); \
+    else P32_LAUNCH_S(TA_, TB_, TinyTile)
     if (!ta && !tb) { P32_LAUNCH_T(false, false); }
     else if (!ta && tb) { P32_LAUNCH_T(false, true); }
     else if (ta && !tb) { P32_LAUNCH_T(true, false); }

@@ -38,11 +38,14 @@ namespace p32 {
 // PREFETCH: the raw words of the next k-tile are loaded into registers
 // before the current k-tile is computed (fewer resident waves have to hide
 // the load latency); off for the big tile, whose register budget is spent.
-template <int TM_, int TN_, int TX_, int TY_, bool PREFETCH_>
+// LATENCY: every k-step on the checked path, whose rounding is computed
+// (no table lookup on the accumulator's dependency chain): for launches with
+// about one wave per compute unit, where nothing hides that latency.
+template <int TM_, int TN_, int TX_, int TY_, bool PREFETCH_, bool LATENCY_ = false>
 struct TileShape {
   static constexpr int TM = TM_, TN = TN_, TX = TX_, TY = TY_;
   static constexpr int NT = TX * TY, BM = TY * TM, BN = TX * TN, BK = P32_GEMM_BK;
-  static constexpr bool PREFETCH = PREFETCH_;
+  static constexpr bool PREFETCH = PREFETCH_, LATENCY = LATENCY_;
 };
 // 64 x 32 outputs per 256 threads: the Rgemm of large shapes, the batched
 // kernels and the factorisations' updates
@@ -51,6 +54,7 @@ using BigTile = TileShape<P32_GEMM_TM, P32_GEMM_TN, 16, 16, false>;
 // every compute unit several big tiles
 using MidTile = TileShape<2, 2, 16, 16, true>;
 using SmallTile = TileShape<1, 1, 8, 8, true>;
+using TinyTile = TileShape<1, 1, 8, 8, true, true>;
 // 64 x 16 per 256 threads: updates of at most 16 columns (the right-hand
 // sides of the batched solves, narrow panel remainders)
 using ThinTile = TileShape<4, 1, 16, 16, false>;
@@ -71,20 +75,22 @@ static __device__ __noinline__ win madd_slow(win acc, int32_t a8, int32_t sca, i
   return add_slow(acc, mul_slow(a8, sca, b4, scb));
 }
 
-// epilogue for one element: r = alpha*acc, then r + beta*c
+// epilogue for one element: r = alpha*acc, then r + beta*c (each step on the
+// window-form fast path, which falls back to the exact routines; alpha or
+// beta equal to one multiplies exactly)
 static __device__ __noinline__ uint32_t gemm_epilogue(win acc, int nar, uint32_t alpha, uint32_t beta,
                                                uint32_t c) {
   uint32_t r;
   if (nar || alpha == kNaR) {
     r = kNaR;
   } else {
-    const uint32_t a = encode_exact(acc);
-    r = alpha == kOne ? a : mul_general(decode(alpha), decode(a));
+    const uint32_t a = encode_win(acc);           // acc is exactly a posit
+    r = alpha == kOne ? a : encode_win(mul_win(decode(alpha), decode(a)));
   }
   if (beta != 0u) {
     if (r == kNaR || beta == kNaR || c == kNaR) return kNaR;
-    const uint32_t t = mul_general(decode(beta), decode(c));
-    r = add_general(win_of(r), win_of(t));
+    const uint32_t t = beta == kOne ? c : encode_win(mul_win(decode(beta), decode(c)));
+    r = encode_win(add_win(win_of(r), win_of(t)));
   }
   return r;
 }
@@ -460,7 +466,10 @@ __device__ __forceinline__ void gemm_tile(int64_t m, int64_t n, int64_t k, const
         my_ok &= (acc[i][j].h == 0) | ((unsigned)(acc[i][j].e - EB + 106) <= 206u);
     const bool safe = __syncthreads_and(my_ok);
 
-    if (p0 == 0) {        // first step: accumulators not yet tested, use the checked path
+    if constexpr (S::LATENCY) {
+      P32_UNROLL_(UNROLL)
+      for (int p = 0; p < BK; ++p) k_step<true, S>(acc, As[p], Bs[p], lut, tx, ty);
+    } else if (p0 == 0) {  // first step: accumulators not yet tested, use the checked path
       k_step<true, S>(acc, As[0], Bs[0], lut, tx, ty);
       if (safe) {
 #pragma unroll 1

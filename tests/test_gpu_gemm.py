@@ -61,19 +61,23 @@ def test_ragged_scaled(P, m, n, k, ta, tb):
 
 # The library picks the workgroup tile from the output shape: 64 x 32 tiles
 # when there are at least four per compute unit (1024 on MI355X), else 32 x 32
-# tiles when there are at least two per compute unit, else 8 x 8 tiles.  The
-# shapes below land in each regime, ragged in every dimension.
+# tiles when there are at least two per compute unit, else 8 x 8 tiles, with
+# only checked k-steps when there are fewer than two of those per compute unit.
+# The shapes below land in each regime, ragged in every dimension.
 @pytest.mark.parametrize("m,n,k,ta,tb,regime", [
     (2049, 1057, 37, 0, 0, "64x32"), (1057, 2049, 19, 1, 1, "64x32"), (1100, 1901, 5, 0, 1, "64x32"),
     (700, 801, 45, 0, 0, "32x32"), (801, 700, 33, 1, 0, "32x32"), (769, 735, 17, 1, 1, "32x32"),
-    (511, 513, 70, 0, 1, "8x8"), (9, 2000, 65, 0, 0, "8x8"), (300, 7, 100, 1, 0, "8x8"),
+    (511, 513, 70, 0, 1, "8x8"), (300, 300, 70, 1, 1, "8x8"),
+    (9, 2000, 65, 0, 0, "8x8 checked"), (300, 7, 100, 1, 0, "8x8 checked"), (128, 128, 128, 0, 0, "8x8 checked"),
 ])
 def test_tile_regimes(P, m, n, k, ta, tb, regime):
     """Each workgroup-tile regime of the Rgemm launch (picked from m and n),
     all transposes, NaR/zero sprinkle, against the oracle bit for bit."""
     big = -(-m // 64) * -(-n // 32)
     mid = -(-m // 32) * -(-n // 32)
-    want_regime = "64x32" if big >= 1024 else ("32x32" if mid >= 512 else "8x8")
+    small = -(-m // 8) * -(-n // 8)
+    want_regime = ("64x32" if big >= 1024 else "32x32" if mid >= 512 else "8x8" if small >= 512
+                   else "8x8 checked")
     assert want_regime == regime
     case = W.gemm_scaled(m, n, k, seed=m + 3 * n + 7 * k, sprinkle=1e-4)
     A, B, C, _, _ = case_patterns(case)

@@ -207,6 +207,18 @@ int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, p
                         const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
 
 /*
+ * posit32_getrf_phases -- a diagnostic: posit32_getrf (same arguments,
+ *   validation and result bits), with HIP events recorded between its
+ *   launches; returns after the stream has reached the last of them, with
+ *   ms[0..3] (HOST memory) the milliseconds spent in the panel
+ *   factorisations, the row interchanges outside the panels, the U12 solves
+ *   and the trailing updates, summed over the panels.  Errors as
+ *   posit32_getrf, -8 ms NULL.
+ */
+int posit32_getrf_phases(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
+                         int32_t* ipiv, int32_t* info, double* ms);
+
+/*
  * posit32_getrf_noalloc -- posit32_getrf (same arguments, validation, order
  *   of operations and result bits) for callers that cannot allocate device
  *   memory: code under stream capture by a harness that forbids hipMalloc,

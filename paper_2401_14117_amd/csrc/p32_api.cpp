@@ -103,6 +103,19 @@ int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, p
   return p32::launch_getrf_group((hipStream_t)stream, count, n, nb, A, lda, ipiv, info);
 }
 
+int posit32_getrf_phases(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda, int32_t* ipiv,
+                         int32_t* info, double* ms) {
+  if (n < 0) return -2;
+  if (nb < 1 || nb > 256) return -3;
+  if (n > 0 && A == nullptr) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && ipiv == nullptr) return -6;
+  if (info == nullptr) return -7;
+  if (ms == nullptr) return -8;
+  if (n > 0xFFFFFE) return -2;
+  return p32::launch_getrf_phases((hipStream_t)stream, n, nb, A, lda, ipiv, info, ms);
+}
+
 int posit32_getrf_noalloc(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda,
                           int32_t* ipiv, int32_t* info) {
   if (n < 0) return -2;

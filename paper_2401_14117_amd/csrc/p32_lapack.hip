@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <vector>
 
 #include "p32_chain.hpp"
 #include "p32_device.hpp"
@@ -900,10 +901,41 @@ static int getrf_setup(int64_t gcap, int* cus, int* per_cu_lds, int* per_cu_glb,
   return 0;
 }
 
+// Optional timing of getrf's phases with HIP events recorded between its
+// launches: the time from one mark to the next goes to the phase the later
+// mark closes (0 panel, 1 interchanges, 2 U12 solve, 3 trailing update).
+struct PhaseClock {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  int mark(int ph) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    ev.push_back(e);
+    phase.push_back(ph);
+    return hipEventRecord(e, s) == hipSuccess ? 0 : -1;
+  }
+  // waits for the last mark; ms[0..3] receive the sums
+  int collect(double* ms) {
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+    int rc = ev.empty() || hipEventSynchronize(ev.back()) == hipSuccess ? 0 : -1;
+    for (size_t i = 1; i < ev.size() && rc == 0; ++i) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[i - 1], ev[i]) != hipSuccess) rc = -1;
+      else if (phase[i] >= 0 && phase[i] < 4) ms[phase[i]] += t;
+    }
+    return rc;
+  }
+  ~PhaseClock() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 // getrf on a caller-provided workspace of getrf_ws_bytes(gmax) bytes (every
 // word is set before the first panel, so its previous contents do not matter)
 static int getrf_run(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
-                     int32_t* info, char* ws, int64_t gmax, int cus, int per_cu_lds, int per_cu_glb) {
+                     int32_t* info, char* ws, int64_t gmax, int cus, int per_cu_lds, int per_cu_glb,
+                     PhaseClock* clk = nullptr) {
   const size_t slot_bytes = (size_t)2 * gmax * sizeof(unsigned long long);
   const size_t row_bytes = (size_t)2 * gmax * kMaxNB * sizeof(unsigned long long);
   unsigned long long* slot = reinterpret_cast<unsigned long long*>(ws);
@@ -930,20 +962,26 @@ static int getrf_run(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t 
     void* args[] = {&A, &lda, &n, &j, &jb_i, &R_i, &slot, &crow, &rowc, &ipiv, &info};
     const void* fn = lds ? reinterpret_cast<const void*>(&lu_panel_kernel<true>)
                          : reinterpret_cast<const void*>(&lu_panel_kernel<false>);
+    if (clk && clk->mark(-1)) rc = -1000 - (int)hipErrorUnknown;
     const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)G), dim3(kPanelThreads), args, 0, s);
     if (e != hipSuccess) {
       rc = -1000 - (int)e;
       break;
     }
+    if (clk && clk->mark(0)) rc = -1000 - (int)hipErrorUnknown;
     if (n - jb > 0)
       hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((n - jb + 255) / 256)), dim3(256), 0, s, A, lda,
                          n, j, jb, ipiv);
+    if (clk && clk->mark(1)) rc = -1000 - (int)hipErrorUnknown;
     const int64_t rest = n - j - jb;
     if (rest > 0) {
       hipLaunchKernelGGL(trsm_lu_kernel, dim3((unsigned)rest), dim3(256), 0, s, A, lda, n, j, jb);
-      rc = launch_gemm_ex(s, 0, 0, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
-                          A + j * lda + j + jb, lda, kOne, A + (j + jb) * lda + j + jb, lda, false,
-                          nullptr);
+      if (clk && clk->mark(2)) rc = -1000 - (int)hipErrorUnknown;
+      const int rg = launch_gemm_ex(s, 0, 0, rest, rest, jb, kMinusOne, A + (j + jb) * lda + j, lda,
+                                    A + j * lda + j + jb, lda, kOne, A + (j + jb) * lda + j + jb, lda, false,
+                                    nullptr);
+      if (rc == 0) rc = rg;
+      if (clk && clk->mark(3)) rc = -1000 - (int)hipErrorUnknown;
     }
     if (rc == 0) rc = launch_status();
   }
@@ -1088,6 +1126,29 @@ int launch_getrf_group(hipStream_t s, int count, const int64_t* n, int64_t nb, u
     if (rc == 0) rc = launch_status();
   }
   e = hipFreeAsync(ws, s);
+  if (rc != 0) return rc;
+  if (e != hipSuccess) return -1000 - (int)e;
+  return launch_status();
+}
+
+// getrf with its phases timed (a diagnostic: synchronises the stream)
+int launch_getrf_phases(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                        int32_t* info, double* ms) {
+  for (int i = 0; i < 4; ++i) ms[i] = 0.0;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, info);
+  if (n == 0) return launch_status();
+  int cus = 0, per_cu_lds = 0, per_cu_glb = 0;
+  int64_t gmax = 0;
+  int rc = getrf_setup(kPanelThreads, &cus, &per_cu_lds, &per_cu_glb, &gmax);
+  if (rc != 0) return rc;
+  char* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, getrf_ws_bytes(gmax), s);
+  if (e != hipSuccess) return -1000 - (int)e;
+  PhaseClock clk;
+  clk.s = s;
+  rc = getrf_run(s, n, nb, A, lda, ipiv, info, ws, gmax, cus, per_cu_lds, per_cu_glb, &clk);
+  e = hipFreeAsync(ws, s);
+  if (rc == 0 && clk.collect(ms) != 0) rc = -1000 - (int)hipErrorUnknown;
   if (rc != 0) return rc;
   if (e != hipSuccess) return -1000 - (int)e;
   return launch_status();

@@ -45,6 +45,10 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
 constexpr int kGetrfGroupMax = P32_GROUP_MAX;
 int launch_getrf_group(hipStream_t s, int count, const int64_t* n, int64_t nb, uint32_t* const* A,
                        const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
+// getrf with its phases timed by HIP events (ms[4]: panel, interchanges, U12
+// solve, trailing update); synchronises the stream
+int launch_getrf_phases(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
+                        int32_t* info, double* ms);
 // getrf on the library's file-scope device scratch (no allocation)
 int launch_getrf_noalloc(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,
                          int32_t* info);

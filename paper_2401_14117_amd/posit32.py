@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.posit32_elementwise.argtypes = [vp, i32, i64, vp, vp, vp]
     L.posit32_getrf.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     L.posit32_getrf_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp]
+    L.posit32_getrf_phases.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
+    L.posit32_getrf_phases.restype = i32
     L.posit32_getrf_group.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp]
     L.posit32_getrf_group.restype = i32
     L.posit32_getrf_noalloc.restype = i32
@@ -326,6 +328,19 @@ def getrf(A: torch.Tensor, nb: int = 256, stream=None):
     _check(lib().posit32_getrf(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(ipiv), _ptr(info)),
            "posit32_getrf")
     return A, ipiv[:n], info
+
+
+def getrf_phases(A: torch.Tensor, nb: int = 256, stream=None):
+    """getrf with its phases timed by HIP events (synchronises the stream);
+    returns (A, ipiv, info, {panel, interchanges, u12_solve, trailing_update} in ms)."""
+    n = _square(A)
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    ms = (ctypes.c_double * 4)()
+    _check(lib().posit32_getrf_phases(_stream(stream), n, nb, _ptr(A), _ld(A), _ptr(ipiv), _ptr(info), ms),
+           "posit32_getrf_phases")
+    names = ("panel", "interchanges", "u12_solve", "trailing_update")
+    return A, ipiv[:n], info, {k: round(v, 3) for k, v in zip(names, ms)}
 
 
 GROUP_MAX = 16

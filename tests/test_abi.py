@@ -82,6 +82,9 @@ def test_factorisation_argument_errors(L):
     assert L.posit32_getrf(None, 4, 64, 8, 3, 8, 8) == -5
     assert L.posit32_getrf(None, 4, 64, 8, 4, None, 8) == -6
     assert L.posit32_getrf(None, 4, 64, 8, 4, 8, None) == -7
+    # the phase-timed getrf validates like getrf, plus its host array
+    assert L.posit32_getrf_phases(None, -1, 256, 8, 1, 8, 8, 8) == -2
+    assert L.posit32_getrf_phases(None, 4, 64, 8, 4, 8, 8, None) == -8
     # the allocation-free getrf validates exactly like getrf
     assert L.posit32_getrf_noalloc(None, -1, 256, 8, 1, 8, 8) == -2
     assert L.posit32_getrf_noalloc(None, 4, 257, 8, 4, 8, 8) == -3

@@ -141,6 +141,21 @@ def test_getrf_group_matches_single_large(P):
         assert torch.equal(Ag, As)
 
 
+def test_getrf_phases_same_bits(P):
+    """The phase-timed getrf (a diagnostic) returns getrf's bits and four
+    non-negative phase times."""
+    import torch
+    rng = np.random.default_rng(79)
+    A = P.from_f64(torch.from_numpy(rng.uniform(-1, 1, (700, 700))).cuda())
+    A1, A2 = A.clone(), A.clone()
+    _, p1, i1 = P.getrf(A1, 256)
+    _, p2, i2, ms = P.getrf_phases(A2, 256)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, A2) and torch.equal(p1, p2) and int(i1.item()) == int(i2.item()) == 0
+    assert set(ms) == {"panel", "interchanges", "u12_solve", "trailing_update"}
+    assert all(v >= 0.0 for v in ms.values()) and ms["panel"] > 0.0
+
+
 def test_exact_recovery_on_gpu(P):
     """Dyadic L*U with pivot-preserving |L| < 1, rows shuffled: the GPU
     returns the exact factors (closed form, independent of the oracle)."""

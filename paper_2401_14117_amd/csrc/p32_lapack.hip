@@ -61,7 +61,10 @@ __device__ __forceinline__ void put4(uint32_t (&v)[4], int u, uint32_t x) {
   else v[3] = x;
 }
 
-constexpr int kPanelThreads = 1024;
+#ifndef P32_PANEL_THREADS
+#define P32_PANEL_THREADS 512    // threads per panel workgroup
+#endif
+constexpr int kPanelThreads = P32_PANEL_THREADS;
 constexpr int kPanelLds = 16384;        // words of panel rows a workgroup keeps in LDS
 constexpr unsigned kPollLimit = 1u << 20;
 

@@ -451,6 +451,24 @@ def _tuning_info(kind: str) -> dict:
     return {"source": os.path.relpath(src, ROOT) if src != "built-in" else src, **t.to_dict()}
 
 
+def _batch_roofline(kind: str, kms: float, pops: float) -> dict | None:
+    """Integer-VALU roofline of the batched kernel: the VALU lane-instructions
+    per multiply-add measured by the committed SQ-counter summary of the
+    same workload, times this run's multiply-adds (factor pops / 2) over this
+    run's kernel time, against the 78.6 T lane-op/s peak."""
+    path = os.path.join(ROOT, "profiles", f"batch_{kind}_valu_rocprof.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"VALU lane-instructions per multiply-add \(whole kernel\) \| ([0-9.]+) \|", open(path).read())
+    if not m:
+        return None
+    per = float(m.group(1))
+    achieved = per * (pops / 2.0) / (kms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT_TOPS, 2),
+            "unit": "Tlane-op/s", "frac": round(achieved / PEAK_INT_TOPS, 4), "traffic": None,
+            "valu_per_madd": per, "valu_per_madd_source": os.path.relpath(path, ROOT)}
+
+
 def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args, graph_same) -> dict:
     return {
         "metric": f"Posit32 batched {'LU' if kind == 'lu' else 'Cholesky'} factor+solve solves/s",
@@ -464,7 +482,7 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
                    "sub_panel_tuning": _tuning_info(kind),
                    "launch": "one persistent kernel captured in a hipGraph; each step is a replay",
                    "graph_bit_identical_to_eager": graph_same, "one_at_a_time": single},
-        "roofline": None,
+        "roofline": _batch_roofline(kind, kms, pops),
         "cpu_baseline": cpu,
     }
 
@@ -688,6 +706,7 @@ def run_extras(args, dev) -> dict:
         out[f"batch_{kind}"] = {
             "solves_per_s": r["value"], "ms_per_batch": r["ms_per_step"], "systems": c["count"],
             "factor_gpops": c["factor_gpops"], "graph_bit_identical_to_eager": c["graph_bit_identical_to_eager"],
+            "roofline_frac": (r["roofline"] or {}).get("frac"),
             "one_at_a_time_solves_per_s": one["solves_per_s"] if one else None,
             "one_at_a_time_bit_identical": one["bit_identical_to_batched"] if one else None,
             "setup_s": c["setup_s"]}

@@ -203,6 +203,21 @@ int posit32_getrf(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda
  *   -7 ipiv NULL or ipiv[i] NULL with n[i] > 0, -8 info NULL or info[i] NULL.
  */
 #define P32_GROUP_MAX 16
+/*
+ * posit32_getrs_group -- posit32_getrs (op = P32_NOTRANS) on count <=
+ *   P32_GROUP_MAX independent systems at once: system i solves A_i X = B_i
+ *   with the factors LU[i] (n[i] x n[i], lda[i]) and pivots ipiv[i] of
+ *   posit32_getrf, B[i] n[i] x nrhs[i] with leading dimension ldb[i],
+ *   overwritten by X bit for bit as posit32_getrs would.  The substitutions of
+ *   all systems advance 64 rows at a time together (one launch per block
+ *   step for every system's diagonal block, one for every system's rows
+ *   beyond it).  Host arrays of device pointers; nrhs[i] <= 65535; the B[i]
+ *   must not overlap.  Allocates nothing.  Errors: -2 count, -3 n, -4 nrhs,
+ *   -5 LU, -6 lda, -7 ipiv, -8 B (also two systems sharing one), -9 ldb.
+ */
+int posit32_getrs_group(void* stream, int count, const int64_t* n, const int64_t* nrhs,
+                        const posit32_t* const* LU, const int64_t* lda, const int32_t* const* ipiv,
+                        posit32_t* const* B, const int64_t* ldb);
 int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, posit32_t* const* A,
                         const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
 

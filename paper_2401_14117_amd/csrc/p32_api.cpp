@@ -103,6 +103,37 @@ int posit32_getrf_group(void* stream, int count, const int64_t* n, int64_t nb, p
   return p32::launch_getrf_group((hipStream_t)stream, count, n, nb, A, lda, ipiv, info);
 }
 
+int posit32_getrs_group(void* stream, int count, const int64_t* n, const int64_t* nrhs, const posit32_t* const* LU,
+                        const int64_t* lda, const int32_t* const* ipiv, posit32_t* const* B, const int64_t* ldb) {
+  if (count < 0 || count > P32_GROUP_MAX) return -2;
+  if (count == 0) return 0;
+  if (n == nullptr) return -3;
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 0) return -3;
+  if (nrhs == nullptr) return -4;
+  for (int i = 0; i < count; ++i)
+    if (nrhs[i] < 0 || nrhs[i] > 65535) return -4;
+  if (LU == nullptr) return -5;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 0 && LU[i] == nullptr) return -5;
+  if (lda == nullptr) return -6;
+  for (int i = 0; i < count; ++i)
+    if (lda[i] < (n[i] > 1 ? n[i] : 1)) return -6;
+  if (ipiv == nullptr) return -7;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 0 && ipiv[i] == nullptr) return -7;
+  if (B == nullptr) return -8;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 0 && nrhs[i] > 0 && B[i] == nullptr) return -8;
+  if (ldb == nullptr) return -9;
+  for (int i = 0; i < count; ++i)
+    if (ldb[i] < (nrhs[i] > 1 ? nrhs[i] : 1)) return -9;
+  for (int i = 0; i < count; ++i)                  // right-hand sides must not be shared
+    for (int k = 0; k < i; ++k)
+      if (n[i] > 0 && nrhs[i] > 0 && n[k] > 0 && nrhs[k] > 0 && B[i] == B[k]) return -8;
+  return p32::launch_getrs_group((hipStream_t)stream, count, n, nrhs, LU, lda, ipiv, B, ldb);
+}
+
 int posit32_getrf_phases(void* stream, int64_t n, int64_t nb, posit32_t* A, int64_t lda, int32_t* ipiv,
                          int32_t* info, double* ms) {
   if (n < 0) return -2;

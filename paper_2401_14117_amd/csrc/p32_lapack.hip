@@ -675,16 +675,20 @@ __device__ __forceinline__ uint32_t tri_coef(const uint32_t* M, int64_t lda, int
 // on the chain itself.
 constexpr int kTrsvBlock = 64;
 
+struct TrsvShared {
+  int2 coef[kTrsvBlock][kTrsvBlock + 1];
+  lut_t lut[256];
+};
+
 template <int kind>
-__global__ void __launch_bounds__(kTrsvBlock)
-trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
-                 int64_t nrhs, int64_t s, int bs) {
-  __shared__ int2 coef[kTrsvBlock][kTrsvBlock + 1];
-  __shared__ lut_t lut[256];
+__device__ __forceinline__ void trsv_diag_body(TrsvShared& sh, const uint32_t* __restrict__ M, int64_t lda,
+                                               uint32_t* __restrict__ B, int64_t ldb, int64_t s, int bs,
+                                               int64_t q) {
+  auto& coef = sh.coef;
+  auto& lut = sh.lut;
   constexpr bool forward = kind_forward(kind);
   constexpr bool unit = kind_unit(kind);
   const int lane = threadIdx.x;
-  const int64_t q = blockIdx.x;
   // coef[r][u]: coefficient of the u-th column in solve order in row r,
   // decoded; only the entries strictly below the diagonal in solve order are
   // loaded.  The lane index is u (kinds 0..2: a row of M is contiguous) or r
@@ -757,6 +761,14 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
   if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(unbias(acc));
 }
 
+template <int kind>
+__global__ void __launch_bounds__(kTrsvBlock)
+trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
+                 int64_t nrhs, int64_t s, int bs) {
+  __shared__ TrsvShared sh;
+  trsv_diag_body<kind>(sh, M, lda, B, ldb, s, bs, blockIdx.x);
+}
+
 // Rows outside the diagonal block [s, s+bs) get that block's columns, in
 // ascending order (forward) or descending order (backward).  One wave per 64
 // rows and one right-hand side q: lane u holds the block's u-th solved entry
@@ -766,19 +778,21 @@ trsv_diag_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restri
 // step by step.  A NaR among the block's entries reaches every row.
 constexpr int kTrsvChunk = 16;
 
-__global__ void __launch_bounds__(kTrsvBlock)
-trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
-                   int64_t nrhs, int64_t s, int bs, int64_t r0, int64_t r1, int kind) {
-  __shared__ lut_t lut[256];
+// bx: the 64-row chunk of [r0, r1) this workgroup updates; right-hand sides
+// q0, q0 + qstep, ... below nrhs
+__device__ __forceinline__ void trsv_update_body(lut_t* lut, const uint32_t* __restrict__ M, int64_t lda,
+                                                 uint32_t* __restrict__ B, int64_t ldb, int64_t nrhs, int64_t s,
+                                                 int bs, int64_t r0, int64_t r1, int kind, unsigned bx,
+                                                 int64_t q0, int64_t qstep) {
   for (int i = threadIdx.x; i < 256; i += kTrsvBlock) lut[i] = make_lut_entry(i);
   __syncthreads();
   const bool forward = kind_forward(kind);
   const int lane = threadIdx.x;
-  const int64_t r = r0 + (int64_t)blockIdx.x * kTrsvBlock + lane;
+  const int64_t r = r0 + (int64_t)bx * kTrsvBlock + lane;
   const bool mine = r < r1;
   const int64_t rr = mine ? r : r0;               // a row in range, for the coefficient loads
   const int64_t cl = forward ? s + lane : s + bs - 1 - lane;
-  for (int64_t q = blockIdx.y; q < nrhs; q += gridDim.y) {
+  for (int64_t q = q0; q < nrhs; q += qstep) {
     const uint32_t bl = lane < bs ? B[cl * ldb + q] : 0u;
     const int2 xs = stage_b(decode(bl));          // NaR stages as zero; flagged below
     const bool bnar = __ballot(bl == kNaR) != 0ull;
@@ -819,11 +833,18 @@ trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __rest
   }
 }
 
+__global__ void __launch_bounds__(kTrsvBlock)
+trsv_update_kernel(const uint32_t* __restrict__ M, int64_t lda, uint32_t* __restrict__ B, int64_t ldb,
+                   int64_t nrhs, int64_t s, int bs, int64_t r0, int64_t r1, int kind) {
+  __shared__ lut_t lut[256];
+  trsv_update_body(lut, M, lda, B, ldb, nrhs, s, bs, r0, r1, kind, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
 // row interchanges of getrs, in order (reverse: in reverse order, which
 // undoes them), one thread per right-hand side
-__global__ void apply_pivots_kernel(uint32_t* __restrict__ B, int64_t ldb, int64_t n, int64_t nrhs,
-                                    const int32_t* __restrict__ ipiv, int reverse) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void apply_pivots_body(uint32_t* __restrict__ B, int64_t ldb, int64_t n,
+                                                  int64_t nrhs, const int32_t* __restrict__ ipiv, int reverse,
+                                                  int64_t q) {
   if (q >= nrhs) return;
   for (int64_t t = 0; t < n; ++t) {
     const int64_t c = reverse ? n - 1 - t : t;
@@ -834,6 +855,64 @@ __global__ void apply_pivots_kernel(uint32_t* __restrict__ B, int64_t ldb, int64
       B[p * ldb + q] = x;
     }
   }
+}
+
+__global__ void apply_pivots_kernel(uint32_t* __restrict__ B, int64_t ldb, int64_t n, int64_t nrhs,
+                                    const int32_t* __restrict__ ipiv, int reverse) {
+  apply_pivots_body(B, ldb, n, nrhs, ipiv, reverse, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---- getrs on several systems at once -------------------------------------------
+// The forward and backward substitutions of up to kGroupMax systems advance
+// block by block together: at block step b, one launch solves the b-th
+// diagonal block (in solve order) of every system that has one, and one
+// launch updates every such system's rows beyond it (system = blockIdx.y or
+// blockIdx.z).  Each system gets exactly the operations of its own getrs.
+struct SolveGroup {
+  int count;
+  const uint32_t* LU[kGroupMax];
+  const int32_t* ipiv[kGroupMax];
+  uint32_t* B[kGroupMax];
+  int64_t n[kGroupMax], nrhs[kGroupMax], lda[kGroupMax], ldb[kGroupMax];
+};
+
+// block b of system s in solve order: its first row and size
+__device__ __forceinline__ bool solve_block(const SolveGroup& g, int sys, bool forward, int64_t b, int64_t& s0,
+                                            int& bs) {
+  const int64_t n = g.n[sys], nblk = (n + kTrsvBlock - 1) / kTrsvBlock;
+  if (b >= nblk || g.nrhs[sys] == 0) return false;
+  s0 = forward ? b * kTrsvBlock : (nblk - 1 - b) * kTrsvBlock;
+  bs = (int)(s0 + kTrsvBlock < n ? kTrsvBlock : n - s0);
+  return true;
+}
+
+__global__ void apply_pivots_group_kernel(SolveGroup g) {
+  const int sys = blockIdx.y;
+  apply_pivots_body(g.B[sys], g.ldb[sys], g.n[sys], g.nrhs[sys], g.ipiv[sys], 0,
+                    (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int kind>
+__global__ void __launch_bounds__(kTrsvBlock) trsv_diag_group_kernel(SolveGroup g, int64_t b) {
+  __shared__ TrsvShared sh;
+  const int sys = blockIdx.y;
+  int64_t s0;
+  int bs;
+  if (!solve_block(g, sys, kind_forward(kind), b, s0, bs) || (int64_t)blockIdx.x >= g.nrhs[sys]) return;
+  trsv_diag_body<kind>(sh, g.LU[sys], g.lda[sys], g.B[sys], g.ldb[sys], s0, bs, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kTrsvBlock) trsv_update_group_kernel(SolveGroup g, int64_t b, int kind) {
+  __shared__ lut_t lut[256];
+  const int sys = blockIdx.z;
+  int64_t s0;
+  int bs;
+  const bool forward = kind_forward(kind);
+  if (!solve_block(g, sys, forward, b, s0, bs)) return;
+  const int64_t r0 = forward ? s0 + bs : 0, r1 = forward ? g.n[sys] : s0;
+  if (r0 + (int64_t)blockIdx.x * kTrsvBlock >= r1) return;
+  trsv_update_body(lut, g.LU[sys], g.lda[sys], g.B[sys], g.ldb[sys], g.nrhs[sys], s0, bs, r0, r1, kind,
+                   blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 __global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
@@ -1317,6 +1396,45 @@ static int potrf_lower(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_
   e = hipFreeAsync(saved, s);
   if (rc != 0) return rc;
   if (e != hipSuccess) return -1000 - (int)e;
+  return launch_status();
+}
+
+int launch_getrs_group(hipStream_t s, int count, const int64_t* n, const int64_t* nrhs, const uint32_t* const* LU,
+                       const int64_t* lda, const int32_t* const* ipiv, uint32_t* const* B, const int64_t* ldb) {
+  if (count < 0 || count > kGroupMax) return -1;
+  SolveGroup g{};
+  int64_t nmax = 0, rmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] == 0 || nrhs[i] == 0) continue;
+    const int c = g.count++;
+    g.LU[c] = LU[i];
+    g.ipiv[c] = ipiv[i];
+    g.B[c] = B[i];
+    g.n[c] = n[i];
+    g.nrhs[c] = nrhs[i];
+    g.lda[c] = lda[i];
+    g.ldb[c] = ldb[i];
+    nmax = n[i] > nmax ? n[i] : nmax;
+    rmax = nrhs[i] > rmax ? nrhs[i] : rmax;
+  }
+  if (g.count == 0) return 0;
+  if (rmax > 65535) return -1;                   // one diagonal workgroup per right-hand side in y
+  hipLaunchKernelGGL(apply_pivots_group_kernel, dim3((unsigned)((rmax + 63) / 64), (unsigned)g.count), dim3(64),
+                     0, s, g);
+  const int64_t nblk = (nmax + kTrsvBlock - 1) / kTrsvBlock;
+  const unsigned gy = (unsigned)(rmax < 65535 ? rmax : 65535);
+  const unsigned gx_upd = (unsigned)((nmax + kTrsvBlock - 1) / kTrsvBlock);
+  for (int kind = 0; kind < 2; ++kind)
+    for (int64_t b = 0; b < nblk; ++b) {
+      if (kind == 0)
+        hipLaunchKernelGGL(trsv_diag_group_kernel<0>, dim3((unsigned)rmax, (unsigned)g.count), dim3(kTrsvBlock), 0,
+                           s, g, b);
+      else
+        hipLaunchKernelGGL(trsv_diag_group_kernel<1>, dim3((unsigned)rmax, (unsigned)g.count), dim3(kTrsvBlock), 0,
+                           s, g, b);
+      hipLaunchKernelGGL(trsv_update_group_kernel, dim3(gx_upd, gy, (unsigned)g.count), dim3(kTrsvBlock), 0, s, g,
+                         b, kind);
+    }
   return launch_status();
 }
 

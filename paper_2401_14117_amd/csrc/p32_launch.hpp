@@ -45,6 +45,10 @@ int launch_getrf(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda,
 constexpr int kGetrfGroupMax = P32_GROUP_MAX;
 int launch_getrf_group(hipStream_t s, int count, const int64_t* n, int64_t nb, uint32_t* const* A,
                        const int64_t* lda, int32_t* const* ipiv, int32_t* const* info);
+// getrs (A X = B) on count <= kGetrfGroupMax systems advanced block by block
+// together (host arrays); each system's results are those of launch_getrs
+int launch_getrs_group(hipStream_t s, int count, const int64_t* n, const int64_t* nrhs, const uint32_t* const* LU,
+                       const int64_t* lda, const int32_t* const* ipiv, uint32_t* const* B, const int64_t* ldb);
 // getrf with its phases timed by HIP events (ms[4]: panel, interchanges, U12
 // solve, trailing update); synchronises the stream
 int launch_getrf_phases(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int64_t lda, int32_t* ipiv,

@@ -386,15 +386,36 @@ int start_batch(posit32_queue* q, Slot& s) {
     }
     rc = p32::launch_getrf_group(q->compute, c, n, q->cfg.nb, A, lda, ipiv, info);
   }
+  // and all their solves (new and resident factors) go together too
+  std::vector<Req*> lu_all;
+  for (Req* r : large)
+    if (r->kind == 0) lu_all.push_back(r);
+  for (size_t g0 = 0; g0 < lu_all.size() && !rc; g0 += p32::kGetrfGroupMax) {
+    const int c = (int)std::min(lu_all.size() - g0, (size_t)p32::kGetrfGroupMax);
+    int64_t n[p32::kGetrfGroupMax], nrhs[p32::kGetrfGroupMax], ld[p32::kGetrfGroupMax];
+    const uint32_t* LU[p32::kGetrfGroupMax];
+    const int32_t* ipiv[p32::kGetrfGroupMax];
+    uint32_t* B[p32::kGetrfGroupMax];
+    for (int i = 0; i < c; ++i) {
+      Req* r = lu_all[g0 + i];
+      n[i] = r->n;
+      nrhs[i] = r->nrhs;
+      ld[i] = r->n;
+      LU[i] = (const uint32_t*)(pool + r->fac_off);
+      ipiv[i] = (const int32_t*)(pool + r->fac_off + round_up((size_t)r->n * r->n * 4));
+      B[i] = (uint32_t*)(pool + r->rhs_off);
+    }
+    // right-hand sides in the ldb array (B is n x nrhs, row stride nrhs)
+    rc = p32::launch_getrs_group(q->compute, c, n, nrhs, LU, ld, ipiv, B, nrhs);
+  }
   for (Req* r : large) {
     if (rc) break;
     uint32_t* A = (uint32_t*)(pool + r->fac_off);
     uint32_t* B = (uint32_t*)(pool + r->rhs_off);
-    int32_t* ipiv = (int32_t*)(pool + r->fac_off + round_up((size_t)r->n * r->n * 4));
     int32_t* info = dinfo + sub;
     r->info = sub++;
     if (r->kind == 0) {
-      if (!rc) rc = p32::launch_getrs(q->compute, 0, r->n, r->nrhs, A, r->n, ipiv, B, r->nrhs);
+      continue;                                  // factored and solved above
     } else {
       if (!r->factor_in) rc = p32::launch_potrf(q->compute, 0, r->n, q->cfg.nb, A, r->n, info);
       if (!rc) rc = p32::launch_potrs(q->compute, 0, r->n, r->nrhs, A, r->n, B, r->nrhs);

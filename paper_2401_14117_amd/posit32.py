@@ -114,6 +114,8 @@ def lib() -> ctypes.CDLL:
     L.posit32_getrf_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     L.posit32_getrf_phases.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
     L.posit32_getrf_phases.restype = i32
+    L.posit32_getrs_group.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.posit32_getrs_group.restype = i32
     L.posit32_getrf_group.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp]
     L.posit32_getrf_group.restype = i32
     L.posit32_getrf_noalloc.restype = i32
@@ -361,6 +363,24 @@ def getrf_group(As, nb: int = 256, stream=None):
     Ip = (ctypes.c_void_p * max(count, 1))(*[i.data_ptr() for i in infos])
     _check(lib().posit32_getrf_group(_stream(stream), count, ns, nb, Ap, ldas, Pp, Ip), "posit32_getrf_group")
     return [(A, p[:A.shape[0]], i) for A, p, i in zip(As, ipivs, infos)]
+
+
+def getrs_group(LUs, ipivs, Bs, stream=None):
+    """In place A_i X_i = B_i for up to GROUP_MAX systems at once
+    (posit32_getrs_group) with the factors of getrf; returns Bs."""
+    count = len(LUs)
+    if count > GROUP_MAX or len(ipivs) != count or len(Bs) != count:
+        raise ValueError(f"at most {GROUP_MAX} systems, one pivot vector and right-hand side each")
+    B2 = [_rhs(B, _square(LU)) for LU, B in zip(LUs, Bs)]
+    c = max(count, 1)
+    ns = (ctypes.c_int64 * c)(*[LU.shape[0] for LU in LUs])
+    rs = (ctypes.c_int64 * c)(*[B.shape[1] for B in B2])
+    ldas = (ctypes.c_int64 * c)(*[_ld(LU) for LU in LUs])
+    ldbs = (ctypes.c_int64 * c)(*[_ld(B) for B in B2])
+    P = lambda ts: (ctypes.c_void_p * c)(*[t.data_ptr() for t in ts])
+    _check(lib().posit32_getrs_group(_stream(stream), count, ns, rs, P(LUs), ldas, P(ipivs), P(B2), ldbs),
+           "posit32_getrs_group")
+    return Bs
 
 
 def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, stream=None,

@@ -107,6 +107,17 @@ def test_factorisation_argument_errors(L):
     assert L.posit32_getrf_group(None, 2, n2, 64, p2, I64x2(4, 2), p2, p2) == -6
     assert L.posit32_getrf_group(None, 2, n2, 64, p2, ld2, None, p2) == -7
     assert L.posit32_getrf_group(None, 2, n2, 64, p2, ld2, p2, Px2(8, None)) == -8
+    # getrs_group(stream, count, n[], nrhs[], LU[], lda[], ipiv[], B[], ldb[])
+    r2 = I64x2(1, 2)
+    assert L.posit32_getrs_group(None, 17, n2, r2, p2, ld2, p2, p2, r2) == -2
+    assert L.posit32_getrs_group(None, 0, None, None, None, None, None, None, None) == 0
+    assert L.posit32_getrs_group(None, 2, I64x2(-1, 3), r2, p2, ld2, p2, p2, r2) == -3
+    assert L.posit32_getrs_group(None, 2, n2, I64x2(1, 70000), p2, ld2, p2, p2, r2) == -4
+    assert L.posit32_getrs_group(None, 2, n2, r2, Px2(None, 8), ld2, p2, p2, r2) == -5
+    assert L.posit32_getrs_group(None, 2, n2, r2, p2, I64x2(3, 3), p2, p2, r2) == -6
+    assert L.posit32_getrs_group(None, 2, n2, r2, p2, ld2, None, p2, r2) == -7
+    assert L.posit32_getrs_group(None, 2, n2, r2, p2, ld2, p2, Px2(8, 8), r2) == -8
+    assert L.posit32_getrs_group(None, 2, n2, r2, p2, ld2, p2, p2, I64x2(1, 1)) == -9
     # getrs(stream, op, n, nrhs, LU, lda, ipiv, B, ldb)
     assert L.posit32_getrs(None, 2, 4, 1, 8, 4, 8, 8, 1) == -2
     assert L.posit32_getrs(None, -1, 4, 1, 8, 4, 8, 8, 1) == -2

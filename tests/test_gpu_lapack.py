@@ -124,6 +124,25 @@ def test_getrf_group_parity(P):
             assert np.array_equal(from_dev(Ad), LU), _diff(from_dev(Ad), LU)
 
 
+def test_getrs_group_matches_single(P):
+    """posit32_getrs_group on systems of mixed sizes and right-hand-side
+    counts (special factors with NaR and zero diagonals among them): every
+    solution equals posit32_getrs on it alone, and the oracle's."""
+    import torch
+    cases = [_solve_case(n, r, w) for n, r, w in ((150, 5, "u"), (1, 1, "b"), (200, 2, "z"), (65, 70, "l"),
+                                                  (64, 1, "u"), (130, 3, "b"))]
+    LUs = [to_dev(M) for M, _, _ in cases]
+    pivs = [torch.from_numpy(ip).cuda() for _, _, ip in cases]
+    Bg = [to_dev(B) for _, B, _ in cases]
+    P.getrs_group(LUs, pivs, Bg)
+    for (M, B, ip), LU, pv, bg in zip(cases, LUs, pivs, Bg):
+        Bs = to_dev(B)
+        P.getrs(LU, pv, Bs)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(bg), from_dev(Bs))
+        assert np.array_equal(from_dev(bg), O.getrs(M, ip, B))
+
+
 def test_getrf_group_matches_single_large(P):
     """A group of the serving workload's larger sizes (600..2048): every
     system bit-identical to posit32_getrf on it alone."""

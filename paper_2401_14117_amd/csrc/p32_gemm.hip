@@ -103,15 +103,10 @@ static int64_t tile_count(int64_t m, int64_t n) {
 // checked k-steps when there are fewer than two of those per compute unit.
 // 0 big, 1 mid, 2 small, 3 tiny.
 static int pick_shape(int64_t m, int64_t n) {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, c = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
-      cus = c;
-    else
-      cus = 256;
-  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
   if (tile_count<BigTile>(m, n) >= 4 * (int64_t)cus) return 0;
   if (tile_count<MidTile>(m, n) >= 2 * (int64_t)cus) return 1;
   if (tile_count<SmallTile>(m, n) >= 2 * (int64_t)cus) return 2;

@@ -408,13 +408,18 @@ int posit32_vbatched_default_tuning(int kind, posit32_vbatch_tuning* out);
  * is the factorisation's (as posit32_getrf / posit32_potrf); a factorisation
  * with info > 0 is not solved and not kept (X is then the unsolved B).  Times
  * are seconds on the host's monotonic clock since the queue was created.
+ * Back-pressure: with cfg->max_pending > 0, posit32_queue_submit returns
+ * P32_E_BUSY (nothing queued) while that many tickets are not yet retired
+ * (submitted and not yet returned by a completed poll or wait); the caller
+ * collects results and submits again.
  * All calls are thread-safe.  Errors: -1 bad queue or cfg (device_bytes below
- * 1 MiB, max_batch < 1, nb outside 1..256, batch_max_n < 0, invalid tuning
- * table), -2 bad request,
+ * 1 MiB, max_batch < 1, nb outside 1..256, batch_max_n < 0, max_pending < 0,
+ * invalid tuning table), -2 bad request,
  * ticket or factor handle, P32_E_NOMEM from submit for a system larger than
  * the pool.  posit32_queue_destroy finishes every submitted request first.
  */
 #define P32_E_NOMEM (-4000)          /* below every P32_E_HIP code */
+#define P32_E_BUSY (-5000)           /* submit: cfg->max_pending tickets not yet retired */
 enum { P32_REQ_LU = 0, P32_REQ_CHOL = 1 };
 
 typedef struct posit32_queue posit32_queue;
@@ -425,6 +430,7 @@ typedef struct {
   int32_t nb;                /* block size of the factorisations */
   int32_t batch_max_n;       /* largest n sent through the batched kernels (see above) */
   const posit32_vbatch_tuning* tuning;   /* NULL, or [LU, Cholesky] tables */
+  int64_t max_pending;       /* 0: no limit; else at most this many tickets not yet retired */
 } posit32_queue_cfg;
 
 typedef struct {

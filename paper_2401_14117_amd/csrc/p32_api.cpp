@@ -13,6 +13,7 @@ int posit32_version(void) { return 200; }
 const char* posit32_strerror(int code) {
   if (code == 0) return "ok";
   if (code == P32_E_NOMEM) return "the system does not fit the queue's device pool";
+  if (code == P32_E_BUSY) return "the queue holds its maximum of unretired requests";
   if (code <= P32_E_HIP) return hipGetErrorString((hipError_t)(P32_E_HIP - code));
   if (code < 0) return "invalid argument (the return value is minus its 1-based position)";
   return "unknown status";

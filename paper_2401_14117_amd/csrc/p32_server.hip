@@ -554,6 +554,7 @@ int posit32_queue_create(const posit32_queue_cfg* cfg, posit32_queue** out) {
   if (cfg->max_batch < 1) return -1;
   if (cfg->nb < 1 || cfg->nb > 256) return -1;
   if (cfg->batch_max_n < 0) return -1;
+  if (cfg->max_pending < 0) return -1;
   auto q = std::make_unique<posit32_queue>();
   for (int kind = 0; kind < 2; ++kind) {
     if (cfg->tuning == nullptr) q->tune[kind] = p32::default_tuning(kind);
@@ -596,6 +597,7 @@ int posit32_queue_submit(posit32_queue* q, const posit32_request* req, uint64_t*
   const size_t nn = (size_t)req->n * req->n, nb = (size_t)req->n * req->nrhs;
   std::lock_guard<std::mutex> lk(q->mu);
   if (q->stop) return -1;
+  if (q->cfg.max_pending > 0 && (int64_t)q->reqs.size() >= q->cfg.max_pending) return P32_E_BUSY;
   if (req->factor) {
     auto it = q->factors.find(req->factor);
     if (it == q->factors.end() || it->second.released || it->second.kind != req->kind ||

@@ -28,10 +28,16 @@ _lib = None
 
 REQ_LU, REQ_CHOL = 0, 1
 E_NOMEM = -4000
+E_BUSY = -5000
 
 
 class Posit32Error(RuntimeError):
-    pass
+    """A library call returned a nonzero status; ``code`` holds it (None when
+    the library itself could not be loaded)."""
+
+    def __init__(self, msg: str, code: int | None = None):
+        super().__init__(msg)
+        self.code = code
 
 
 TUNE_BUCKETS = 8
@@ -71,7 +77,7 @@ class VBatchDesc(ctypes.Structure):
 class QueueCfg(ctypes.Structure):
     _fields_ = [("device_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
                 ("nb", ctypes.c_int32), ("batch_max_n", ctypes.c_int32),
-                ("tuning", ctypes.c_void_p)]
+                ("tuning", ctypes.c_void_p), ("max_pending", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -155,7 +161,7 @@ def lib() -> ctypes.CDLL:
 def _check(rc: int, what: str) -> None:
     if rc != 0:
         msg = lib().posit32_strerror(rc).decode()
-        raise Posit32Error(f"{what} failed with code {rc}: {msg}")
+        raise Posit32Error(f"{what} failed with code {rc}: {msg}", rc)
 
 
 KIND_CODES = {"lu": 0, "chol": 1}
@@ -543,14 +549,14 @@ class Queue:
     are bit-identical to the batched and single-matrix calls."""
 
     def __init__(self, device_bytes: int = 2 << 30, max_batch: int = 1024, nb: int = 256,
-                 batch_max_n: int = 512):
+                 batch_max_n: int = 512, max_pending: int = 0):
         import numpy as np  # noqa: F401
         tl, tc = active_tuning("lu"), active_tuning("chol")
         self._tunings = None
         if tl is not None or tc is not None:
             self._tunings = (Tuning * 2)(tl or default_tuning("lu"), tc or default_tuning("chol"))
         cfg = QueueCfg(device_bytes, max_batch, nb, batch_max_n,
-                       ctypes.addressof(self._tunings) if self._tunings is not None else None)
+                       ctypes.addressof(self._tunings) if self._tunings is not None else None, max_pending)
         h = ctypes.c_void_p()
         _check(lib().posit32_queue_create(ctypes.byref(cfg), ctypes.byref(h)), "posit32_queue_create")
         self._h = h

@@ -172,7 +172,7 @@ def test_queue_argument_errors(L):
     h = ctypes.c_void_p()
     for cfg in (QueueCfg(1 << 10, 16, 256, 512), QueueCfg(1 << 30, 0, 256, 512),
                 QueueCfg(1 << 30, 16, 0, 512), QueueCfg(1 << 30, 16, 300, 512),
-                QueueCfg(1 << 30, 16, 256, -1)):
+                QueueCfg(1 << 30, 16, 256, -1), QueueCfg(1 << 30, 16, 256, 512, None, -1)):
         assert L.posit32_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
     assert L.posit32_queue_create(None, ctypes.byref(h)) == -1
     t = ctypes.c_uint64()
@@ -180,6 +180,7 @@ def test_queue_argument_errors(L):
     assert L.posit32_factor_release(None, 1) == -1
     assert L.posit32_queue_destroy(None) == -1
     assert L.posit32_strerror(-4000) == b"the system does not fit the queue's device pool"
+    assert L.posit32_strerror(-5000) == b"the queue holds its maximum of unretired requests"
 
 
 def test_vbatched_descriptor_and_tuning_validation(L):

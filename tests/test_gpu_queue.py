@@ -143,6 +143,33 @@ def test_queue_admission_by_footprint(P):
     assert starts == sorted(starts)
 
 
+def test_queue_max_pending(P):
+    """Back-pressure: with max_pending = 2 a third submission is refused with
+    P32_E_BUSY and nothing is queued; once a ticket is retired by wait a
+    submission is accepted again, and every accepted request is solved."""
+    rng = np.random.default_rng(27)
+    n = 64
+    reqs = [(_lu(rng, n), p32(rng.uniform(-1, 1, (n, 2)))) for _ in range(4)]
+    q = P.Queue(device_bytes=64 << 20, max_pending=2)
+    t0 = q.submit(0, reqs[0][1], reqs[0][0])
+    t1 = q.submit(0, reqs[1][1], reqs[1][0])
+    with pytest.raises(P.Posit32Error) as e:
+        q.submit(0, reqs[2][1], reqs[2][0])
+    assert e.value.code == P.E_BUSY
+    out0 = q.wait(t0, 60.0)
+    t3 = q.submit(0, reqs[3][1], reqs[3][0])
+    with pytest.raises(P.Posit32Error) as e:
+        q.submit(0, reqs[2][1], reqs[2][0])      # t1 and t3 still unretired
+    assert e.value.code == P.E_BUSY
+    outs = [out0, q.wait(t1, 60.0), q.wait(t3, 60.0)]
+    st = q.stats()
+    q.close()
+    assert st["pool_used"] == 0
+    for (A, B), out in zip([reqs[0], reqs[1], reqs[3]], outs):
+        X, _ = _alone(P, 0, A, B)
+        assert out["status"] == 0 and np.array_equal(out["X"], X)
+
+
 def test_queue_resident_factor(P):
     rng = np.random.default_rng(24)
     n = 150

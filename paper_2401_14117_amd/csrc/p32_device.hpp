@@ -428,14 +428,8 @@ __device__ __forceinline__ dec dec_of_win(win w) {
 // exact in one fused multiply-add (it is an integer below 2^30), which fixes
 // q up and gives the sticky bit; q, an integer below 2^37, is then read from
 // the bits of its binary64 representation.
-__device__ inline win div_win(dec a, dec b, double rcp_b) {
-  win w;
-  if (a.s == 0) {
-    w.h = 0;
-    w.e = kEZero;
-    return w;
-  }
-  const bool neg = (a.s < 0) != (b.s < 0);
+__device__ __forceinline__ void div_quotient(dec a, dec b, double rcp_b, uint32_t& hi, uint32_t& lo,
+                                             bool& rem) {
   const double ma = (double)(a.s < 0 ? -a.s : a.s);
   const double mb = (double)(b.s < 0 ? -b.s : b.s);
   const double num = ma * 68719476736.0;          // |a.s| 2^36, exact
@@ -446,18 +440,49 @@ __device__ inline win div_win(dec a, dec b, double rcp_b) {
   r = fma(-adj, mb, r);
   // q in [2^35, 2^37): significand bits [51:0] of q hold q below its leading bit
   const uint64_t bits = (uint64_t)__double_as_longlong(q);
-  const uint32_t hi = (uint32_t)(bits >> 32), lo = (uint32_t)bits;
+  hi = (uint32_t)(bits >> 32);
+  lo = (uint32_t)bits;
+  rem = r != 0.0;
+}
+
+// the quotient rounded at a scale sc inside the fast range: the top 30 bits
+// of the significand (leading bit at 29), the rest of it and the remainder
+// folded into bit 0
+__device__ __forceinline__ win div_round_fast(bool neg, uint32_t hi, uint32_t lo, bool rem, int sc) {
+  const uint32_t top = ((hi & 0xFFFFFu) | 0x100000u) << 9 | (lo >> 23);
+  const int32_t h2 = (int32_t)((top & ~1u) | (uint32_t)(((lo & 0xFFFFFFu) != 0u) | rem));
+  return round_h2(neg ? -h2 : h2, sc);            // round to nearest even is odd-symmetric
+}
+
+__device__ inline win div_win(dec a, dec b, double rcp_b) {
+  win w;
+  if (a.s == 0) {
+    w.h = 0;
+    w.e = kEZero;
+    return w;
+  }
+  const bool neg = (a.s < 0) != (b.s < 0);
+  uint32_t hi, lo;
+  bool rem;
+  div_quotient(a, b, rcp_b, hi, lo, rem);
   const int L = (int)(hi >> 20) - 1023;           // 35 or 36
   const int sc = a.sc - b.sc - 36 + L;
-  if (scale_ok(sc)) {
-    // the top 30 bits of the significand (leading bit at 29), the rest of
-    // it and the remainder folded into bit 0
-    const uint32_t top = ((hi & 0xFFFFFu) | 0x100000u) << 9 | (lo >> 23);
-    const int32_t h2 = (int32_t)((top & ~1u) | (uint32_t)(((lo & 0xFFFFFFu) != 0u) | (r != 0.0)));
-    return round_h2(neg ? -h2 : h2, sc);          // round to nearest even is odd-symmetric
-  }
+  if (scale_ok(sc)) return div_round_fast(neg, hi, lo, rem, sc);
   const uint64_t qi = ((((uint64_t)(hi & 0xFFFFFu) | 0x100000u) << 32) | lo) >> (52 - L);
-  return win_of(round_general64(neg, qi, a.sc - b.sc - 36, r != 0.0));
+  return win_of(round_general64(neg, qi, a.sc - b.sc - 36, rem));
+}
+
+// div_win without branches, for chains where one lane's quotient is needed
+// by the whole wave: ok is false when div_win must be called instead (a zero
+// dividend, or a quotient scale outside the fast range); the returned value
+// is then meaningless.  b must be nonzero.
+__device__ __forceinline__ win div_win_fast(dec a, dec b, double rcp_b, bool& ok) {
+  uint32_t hi, lo;
+  bool rem;
+  div_quotient(a, b, rcp_b, hi, lo, rem);
+  const int sc = a.sc - b.sc - 36 + (int)(hi >> 20) - 1023;
+  ok = (a.s != 0) & scale_ok(sc);
+  return div_round_fast((a.s < 0) != (b.s < 0), hi, lo, rem, sc);
 }
 
 // rnd(sqrt(a)) in window form for a decoded a > 0.  With a = m 2^x, x even,

@@ -738,24 +738,40 @@ __device__ __forceinline__ void trsv_diag_body(TrsvShared& sh, const uint32_t* _
     const int cl = forward ? u : bs - 1 - u;                // local column (wave-uniform)
     const int2 m = mnext;
     if (u + 1 < bs) mnext = coef[lane][u + 1];
-    if (!unit && lane == cl) {
-      if (dg_bad) xnar = true;
-      else if (!xnar) acc = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
+    // x[c]: the owner's running value, divided by its diagonal (non-unit
+    // kinds).  Every lane divides its own running value without branches and
+    // the owner's quotient is read with v_readlane, so the chain carries no
+    // exec-mask changes; the exact routine runs only when the owner's
+    // quotient needs it (a wave-uniform branch).
+    win xw = acc;
+    int flags = xnar;                                       // bit 0: NaR, bit 1: exact path
+    if (!unit) {
+      bool ok;
+      xw = bias(div_win_fast(dec_of_win(unbias(acc)), dg, rcp, ok));
+      flags = (xnar | dg_bad) | (ok ? 0 : 2);
+    }
+    const int pf = __builtin_amdgcn_readlane(flags, cl);
+    const bool pnar = (pf & 1) != 0;
+    if (!unit && (pf & 2) && !pnar) {
+      if (lane == cl) xw = bias(div_win(dec_of_win(unbias(acc)), dg, rcp));
     }
     win pc;
-    pc.h = __builtin_amdgcn_readlane(acc.h, cl);
-    pc.e = __builtin_amdgcn_readlane(acc.e, cl);
-    const bool pnar = __builtin_amdgcn_readlane((int)xnar, cl) != 0;
-    const dec dx = dec_of_win(unbias(pc));                 // x[c], wave-uniform
-    const bool below = forward ? lane > cl : lane < cl;
-    if (lane < bs && below) {
-      if (m.y == kScNaR || pnar) xnar = true;
-      else if (!xnar && dx.s != 0) {                       // x[c] = 0 changes nothing
-        dec md;
-        md.s = m.x;
-        md.sc = m.y;
-        acc = chain_update(acc, md, stage_b(dx), scale_proven(dx.sc), lut);
-      }
+    pc.h = __builtin_amdgcn_readlane(xw.h, cl);
+    pc.e = __builtin_amdgcn_readlane(xw.e, cl);
+    if (!unit && lane == cl) {
+      acc = xw;
+      xnar = pnar;
+    }
+    // every later row r: x[r] - rnd(T(r,c) x[c]); a zero coefficient (also
+    // given to the lanes without an update) leaves the running value as it is
+    const bool act = lane < bs && (forward ? lane > cl : lane < cl);
+    xnar = xnar | (act & ((m.y == kScNaR) | pnar));
+    const dec dx = dec_of_win(unbias(pc));                  // x[c], wave-uniform
+    if (!pnar && dx.s != 0) {                              // x[c] = 0 changes nothing
+      dec md;
+      md.s = act && !xnar ? m.x : 0;
+      md.sc = m.y;
+      acc = chain_update(acc, md, stage_b(dx), scale_proven(dx.sc), lut);
     }
   }
   if (lane < bs) B[(s + lane) * ldb + q] = xnar ? kNaR : encode_win(unbias(acc));
@@ -819,11 +835,15 @@ __device__ __forceinline__ void trsv_update_body(lut_t* lut, const uint32_t* __r
         const int step = c0 + i;
         if (step < bs) {
           const uint32_t m = cur[i];
-          if (m == kNaR) xnar = true;
+          xnar = xnar | (m == kNaR);
           int2 bx;
           bx.x = __builtin_amdgcn_readlane(xs.x, step);
           bx.y = __builtin_amdgcn_readlane(xs.y, step);
-          if (bx.x != 0 && m != kNaR) acc = chain_update(acc, decode(m), bx, scale_proven(bx.y >> 4), lut);
+          if (bx.x != 0) {                        // wave-uniform; a NaR coefficient updates nothing
+            dec md = decode(m);
+            md.s = m == kNaR ? 0 : md.s;
+            acc = chain_update(acc, md, bx, scale_proven(bx.y >> 4), lut);
+          }
         }
       }
 #pragma unroll

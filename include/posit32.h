@@ -321,9 +321,9 @@ int posit32_posv_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb
  * The batched kernels factor each panel in sub-panels of `sub` columns (the
  * unblocked pivot search / division / rank-1 updates inside, fused-update
  * chains through the Rgemm tile routine outside; the solves work in blocks of
- * `sub` rows).  The width only regroups the work -- every element receives
- * its updates in the unblocked order -- so every table gives the same result
- * bits; it changes only the speed.  A system of order n uses sub[b] of the
+ * 64 rows, whatever the table).  The width only regroups the work -- every
+ * element receives its updates in the unblocked order -- so every table gives
+ * the same result bits; it changes only the speed.  A system of order n uses sub[b] of the
  * first bucket b with n <= max_n[b] (the last bucket takes every larger n).
  * paper_2401_14117_amd/autotune.py measures the fastest width per bucket on
  * the device and stores the tables it finds.

@@ -38,9 +38,10 @@
 //    Rgemm(-1, 1, L21, L21^T).
 //
 //  Solves: the row interchanges (LU), then forward and backward substitution
-//  in blocks of `sub` rows: the diagonal block column by column, then one
-//  fused-update chain over the block's columns for all rows beyond it (in
-//  descending column order for the backward pass).
+//  in blocks of 64 rows: the diagonal block column by column (one wave per
+//  right-hand side, one row per lane), then one fused-update chain over the
+//  block's columns for all rows beyond it (in descending column order for
+//  the backward pass).
 //
 // The sub-panel width `sub` only regroups the work: every element still gets
 // its updates in the unblocked order, so any width gives the same bits.  It
@@ -50,6 +51,7 @@
 // factors a small matrix unblocked, with no tile overhead at all.
 #include <hip/hip_runtime.h>
 
+#include "p32_chain.hpp"
 #include "p32_device.hpp"
 #include "p32_gemm_tile.hpp"
 #include "p32_launch.hpp"
@@ -253,10 +255,125 @@ __device__ __forceinline__ void lu_factor(uint32_t* A, int64_t lda, int64_t n, i
   }
 }
 
+// ---- substitutions ----------------------------------------------------------
+
+// Diagonal block [c0, c0+w) (w <= kMaxSub) of a triangular solve, for every
+// right-hand side: wave v takes the right-hand sides v, v + 4, v + 8, ...,
+// kSolveQ of them at a time, and lane r owns row c0 + r of each, in window
+// form with a NaR flag.  kind 0: L unit lower, forward (LU); 1: U upper,
+// backward (LU); 2: L lower, forward (Cholesky); 3: L^T, backward (Cholesky).
+// Per column c in solve order, every lane divides its running values by its
+// diagonal without branches (non-unit kinds) and the owner lane's quotient,
+// x[c], is read by all lanes with v_readlane (the exact division runs only
+// when the owner's quotient needs it, a wave-uniform branch); every later row
+// r then gets x[r] - rnd(T(r,c) x[c]) (chain_update), a zero coefficient
+// standing in for the rows without an update.  Each row thus receives the
+// per-column steps of the unblocked substitution in the same order, with no
+// barrier between the columns.  The rounding table is set up in the tile
+// area, which the tiles between the blocks overwrite.
+constexpr int kSolveQ = 4;
+constexpr int kWaves = kBT / 64;
+
+template <int kind>
+__device__ __forceinline__ void diag_solve(const uint32_t* __restrict__ M, int64_t lda, int64_t c0, int w,
+                                           uint32_t* __restrict__ B, int64_t ldb, int64_t nrhs, Shared& sh) {
+  constexpr bool forward = kind == 0 || kind == 2;
+  constexpr bool unit = kind == 0;
+  constexpr bool trans = kind == 3;
+  lut_t* lut = sh.tile.big.lut;
+  static_assert(kBT == 256, "one table entry per thread");
+  lut[threadIdx.x] = make_lut_entry(threadIdx.x);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool mine = lane < w;
+  // this lane's diagonal entry, with its binary64 reciprocal
+  dec dg;
+  dg.s = 0;
+  dg.sc = kEZero;
+  bool dg_bad = true;                            // NaR or zero: quotients are NaR
+  double rcp = 0.0;
+  if (!unit && mine) {
+    const uint32_t dp = M[(c0 + lane) * lda + c0 + lane];
+    dg = decode(dp);
+    dg_bad = dp == kNaR || dg.s == 0;
+    if (!dg_bad) rcp = 1.0 / (double)(dg.s < 0 ? -(int64_t)dg.s : (int64_t)dg.s);
+  }
+  // coefficient T(row c0 + lane, column c0 + cl), 0 for the rows without an update
+  auto coef = [&](int u) -> uint32_t {
+    const int cl = forward ? u : w - 1 - u;
+    const bool act = mine && u < w && (forward ? lane > cl : lane < cl);
+    return act ? (trans ? M[(c0 + cl) * lda + c0 + lane] : M[(c0 + lane) * lda + c0 + cl]) : 0u;
+  };
+  for (int64_t qb = wave; qb < nrhs; qb += kWaves * kSolveQ) {
+    win acc[kSolveQ];
+    bool xnar[kSolveQ];
+#pragma unroll
+    for (int k = 0; k < kSolveQ; ++k) {
+      const int64_t q = qb + kWaves * k;
+      const uint32_t x0 = mine && q < nrhs ? B[(c0 + lane) * ldb + q] : 0u;
+      xnar[k] = x0 == kNaR;
+      acc[k] = mine ? bias(win_of(xnar[k] ? 0u : x0)) : idle_acc();   // biased window form
+    }
+    // coefficients two steps ahead, so that their loads stay off the chain
+    uint32_t m0 = coef(0), m1 = coef(1);
+    for (int u = 0; u < w; ++u) {
+      const int cl = forward ? u : w - 1 - u;      // wave-uniform
+      const uint32_t m = m0;
+      m0 = m1;
+      m1 = coef(u + 2);
+      const bool act = mine && (forward ? lane > cl : lane < cl);
+      dec md = decode(m);
+#pragma unroll
+      for (int k = 0; k < kSolveQ; ++k) {
+        if (qb + kWaves * k >= nrhs) break;         // wave-uniform
+        win xw = acc[k];
+        int flags = xnar[k];                        // bit 0: NaR, bit 1: exact division
+        if (!unit) {
+          bool ok;
+          xw = bias(div_win_fast(dec_of_win(unbias(acc[k])), dg, rcp, ok));
+          flags = (xnar[k] | dg_bad) | (ok ? 0 : 2);
+        }
+        const int pf = __builtin_amdgcn_readlane(flags, cl);
+        const bool pnar = (pf & 1) != 0;
+        if (!unit && (pf & 2) && !pnar) {
+          if (lane == cl) xw = bias(div_win(dec_of_win(unbias(acc[k])), dg, rcp));
+        }
+        win pc;
+        pc.h = __builtin_amdgcn_readlane(xw.h, cl);
+        pc.e = __builtin_amdgcn_readlane(xw.e, cl);
+        if (!unit && lane == cl) {
+          acc[k] = xw;
+          xnar[k] = pnar;
+        }
+        xnar[k] = xnar[k] | (act & ((m == kNaR) | pnar));
+        const dec dx = dec_of_win(unbias(pc));      // x[c], wave-uniform
+        if (!pnar && dx.s != 0) {                  // x[c] = 0 changes nothing
+          dec mk = md;
+          mk.s = act && !xnar[k] ? md.s : 0;
+          acc[k] = chain_update(acc[k], mk, stage_b(dx), scale_proven(dx.sc), lut);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSolveQ; ++k) {
+      const int64_t q = qb + kWaves * k;
+      if (mine && q < nrhs) B[(c0 + lane) * ldb + q] = xnar[k] ? kNaR : encode_win(unbias(acc[k]));
+    }
+  }
+  __syncthreads();
+}
+
+// The substitutions run in blocks of kSolveBlock rows, whatever the
+// factorisation's sub-panel width (the blocking only regroups the work): the
+// diagonal block by diag_solve, whose waves then use all their lanes, and the
+// rows beyond it by one fused-update chain over the block's columns.
+constexpr int kSolveBlock = 64;
+static_assert(kSolveBlock <= kMaxSub && kSolveBlock <= 64, "one row per lane");
+
 // forward (unit lower) and backward (upper) substitution with the LU factors
-__device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_t n, int sub,
-                                         const int32_t* ipiv, uint32_t* B, int64_t ldb, int64_t nrhs,
-                                         Shared& sh) {
+__device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_t n, const int32_t* ipiv,
+                                         uint32_t* B, int64_t ldb, int64_t nrhs, Shared& sh) {
+  constexpr int sub = kSolveBlock;
   const int t = threadIdx.x;
   for (int64_t q = t; q < nrhs; q += kBT)
     for (int64_t c = 0; c < n; ++c) {
@@ -270,30 +387,14 @@ __device__ __forceinline__ void lu_solve(const uint32_t* LU, int64_t lda, int64_
   __syncthreads();
   for (int64_t c0 = 0; c0 < n; c0 += sub) {
     const int w = (int)(sub < n - c0 ? sub : n - c0);
-    for (int cl = 0; cl + 1 < w; ++cl) {
-      const int64_t c = c0 + cl;
-      for_each_rq(w - cl - 1, nrhs, [&](int64_t dr, int64_t q) {
-        const int64_t r = c + 1 + dr;
-        B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
-      });
-      __syncthreads();
-    }
+    diag_solve<0>(LU, lda, c0, w, B, ldb, nrhs, sh);
     const int64_t r1 = c0 + w;
     tiles<false, false, false, true, false>(n - r1, nrhs, w, LU + r1 * lda + c0, lda, B + c0 * ldb, ldb,
                                             B + r1 * ldb, ldb, 0u, 0u, sh);
   }
   for (int64_t c1 = n; c1 > 0; c1 -= sub) {
     const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
-    for (int64_t c = c1 - 1; c >= c0; --c) {
-      const divisor dv = make_divisor(LU[c * lda + c]);
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
-      __syncthreads();
-      for_each_rq(c - c0, nrhs, [&](int64_t dr, int64_t q) {
-        const int64_t r = c0 + dr;
-        B[r * ldb + q] = p_fms(B[r * ldb + q], LU[r * lda + c], B[c * ldb + q]);
-      });
-      __syncthreads();
-    }
+    diag_solve<1>(LU, lda, c0, (int)(c1 - c0), B, ldb, nrhs, sh);
     tiles<false, false, false, true, true>(c0, nrhs, c1 - c0, LU + c0, lda, B + c0 * ldb, ldb, B, ldb, 0u,
                                            0u, sh);
   }
@@ -387,38 +488,19 @@ __device__ __forceinline__ void chol_factor(uint32_t* A, int64_t lda, int64_t n,
   }
 }
 
-__device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64_t n, int sub, uint32_t* B,
-                                           int64_t ldb, int64_t nrhs, Shared& sh) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void chol_solve(const uint32_t* L, int64_t lda, int64_t n, uint32_t* B, int64_t ldb,
+                                           int64_t nrhs, Shared& sh) {
+  constexpr int sub = kSolveBlock;
   for (int64_t c0 = 0; c0 < n; c0 += sub) {
     const int w = (int)(sub < n - c0 ? sub : n - c0);
-    for (int cl = 0; cl < w; ++cl) {
-      const int64_t c = c0 + cl;
-      const divisor dv = make_divisor(L[c * lda + c]);
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
-      __syncthreads();
-      for_each_rq(w - cl - 1, nrhs, [&](int64_t dr, int64_t q) {
-        const int64_t r = c + 1 + dr;
-        B[r * ldb + q] = p_fms(B[r * ldb + q], L[r * lda + c], B[c * ldb + q]);
-      });
-      __syncthreads();
-    }
+    diag_solve<2>(L, lda, c0, w, B, ldb, nrhs, sh);
     const int64_t r1 = c0 + w;
     tiles<false, false, false, true, false>(n - r1, nrhs, w, L + r1 * lda + c0, lda, B + c0 * ldb, ldb,
                                             B + r1 * ldb, ldb, 0u, 0u, sh);
   }
   for (int64_t c1 = n; c1 > 0; c1 -= sub) {
     const int64_t c0 = c1 - sub > 0 ? c1 - sub : 0;
-    for (int64_t c = c1 - 1; c >= c0; --c) {
-      const divisor dv = make_divisor(L[c * lda + c]);
-      for (int64_t q = t; q < nrhs; q += kBT) B[c * ldb + q] = p_div_by(B[c * ldb + q], dv);
-      __syncthreads();
-      for_each_rq(c - c0, nrhs, [&](int64_t dr, int64_t q) {
-        const int64_t r = c0 + dr;
-        B[r * ldb + q] = p_fms(B[r * ldb + q], L[c * lda + r], B[c * ldb + q]);
-      });
-      __syncthreads();
-    }
+    diag_solve<3>(L, lda, c0, (int)(c1 - c0), B, ldb, nrhs, sh);
     // rows above the block: coefficient L[c][r] = op(A)(r, c) with op = transpose
     tiles<true, false, false, true, true>(c0, nrhs, c1 - c0, L + c0 * lda, lda, B + c0 * ldb, ldb, B, ldb,
                                           0u, 0u, sh);
@@ -479,8 +561,8 @@ __global__ void __launch_bounds__(kBT, P32_BATCH_MIN_WAVES) vbatched_kernel(Batc
       else chol_factor(A, lda, n, bt.nb, sub, status, sh);
     }
     if (SOLVE && status == 0 && n > 0 && nrhs > 0) {
-      if (KIND == 0) lu_solve(A, lda, n, sub, ipiv, B, ldb, nrhs, sh);
-      else chol_solve(A, lda, n, sub, B, ldb, nrhs, sh);
+      if (KIND == 0) lu_solve(A, lda, n, ipiv, B, ldb, nrhs, sh);
+      else chol_solve(A, lda, n, B, ldb, nrhs, sh);
     }
     if (threadIdx.x == 0) bt.info[idx] = status;
     __syncthreads();

@@ -169,6 +169,76 @@ def test_chol_vbatched_not_positive_definite(P, bad):
     assert ginfo[1] == info2 == 0 and np.array_equal(np.tril(gA[1]), np.tril(L2))
 
 
+def _factor_like(rng, n, diag_scale=0.0, off_lo=-27, off_hi=-7):
+    """Well-conditioned stand-in factors (the solves take any matrix as L and
+    U): diagonal |d| in [1, 2) 2^diag_scale, off-diagonal entries with scales
+    spread over 2^off_lo .. 2^off_hi, so that the substitutions neither
+    overflow nor cancel and a special value stays where it is put."""
+    M = rng.uniform(0.5, 1.0, (n, n)) * rng.choice([-1.0, 1.0], (n, n)) * 2.0 ** rng.integers(off_lo, off_hi + 1, (n, n))
+    np.fill_diagonal(M, rng.uniform(1.0, 2.0, n) * rng.choice([-1.0, 1.0], n) * 2.0 ** diag_scale)
+    return p32(M)
+
+
+@pytest.mark.parametrize("kind", ["lu", "chol"])
+def test_vbatched_solve_special_values(P, kind):
+    """The batched substitutions alone (the factors given) against the oracle,
+    and the single-matrix substitutions on the same inputs, across 64-row
+    block boundaries: a NaR right-hand side, an all-zero right-hand side
+    (zero quotients, taken by the exact division), a zero and a NaR
+    coefficient on row 0 (LU: only x_0 becomes NaR), a NaR diagonal
+    (Cholesky: every entry NaR), quotients of 2^100 .. 2^110, beyond the
+    fast range, right-hand sides with scales over 2^-30 .. 2^30."""
+    import torch
+    rng = np.random.default_rng(20 if kind == "lu" else 21)
+    sizes = [130, 65, 64, 5, 70, 66]
+    nrhs = [3, 3, 9, 1, 3, 9]
+    mats, rhss, pivs = [], [], []
+    for i, (n, r) in enumerate(zip(sizes, nrhs)):
+        # system 2: diagonals near 2^-100 (LU's U) or 2^-50 (L, divided by twice), so
+        # that the quotients reach 2^100 .. 2^110, beyond the fast range
+        tiny = -100.0 if kind == "lu" else -50.0
+        F = _factor_like(rng, n, diag_scale=tiny if i == 2 else 0.0, off_lo=-130 if i == 2 else -27,
+                         off_hi=-120 if i == 2 else -7)
+        B = p32(rng.uniform(-1, 1, (n, r)) * 2.0 ** (10 if i == 2 else rng.integers(-30, 31, (n, r))))
+        if i == 0:
+            B[100, 1] = 0x80000000                      # NaR right-hand side (column 1 only)
+            B[:, 2] = 0                                 # zero right-hand side
+        if i == 1:
+            if kind == "lu":
+                F[0, 0] = 0                             # zero diagonal: x_0 = NaR
+                F[0, 64] = 0x80000000                   # NaR coefficient in row 0
+            else:
+                F[64, 64] = 0x80000000                  # NaR diagonal
+        if i == 4:
+            B[rng.integers(0, n, 12), rng.integers(0, r, 12)] = 0
+        mats.append(F)
+        rhss.append(B)
+        pivs.append(np.array([int(rng.integers(c, n)) for c in range(n)], dtype=np.int32))
+    As = [to_dev(a) for a in mats]
+    Bs = [to_dev(b) for b in rhss]
+    vb = P.VBatch(As, Bs, lu=kind == "lu")
+    if kind == "lu":
+        for dst, pv in zip(vb.ipivs, pivs):
+            dst.copy_(torch.from_numpy(pv))
+        vb.getrs()
+    else:
+        vb.potrs()
+    torch.cuda.synchronize()
+    assert list(vb.info.cpu().numpy()) == [0] * len(sizes)
+    for i in range(len(sizes)):
+        want = O.getrs(mats[i], pivs[i], rhss[i]) if kind == "lu" else O.potrs(mats[i], rhss[i])
+        got = from_dev(Bs[i])
+        assert np.array_equal(got, want), (i, _diff(got, want))
+        # the single-matrix substitutions on the same inputs
+        Bd = to_dev(rhss[i])
+        if kind == "lu":
+            P.getrs(to_dev(mats[i]), torch.from_numpy(pivs[i]).cuda(), Bd)
+        else:
+            P.potrs(to_dev(mats[i]), Bd)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(Bd), want), (i, _diff(from_dev(Bd), want))
+
+
 def test_vbatched_invalid_systems(P):
     """Invalid systems get a negative info and are left untouched; the rest of
     the batch is unaffected."""

@@ -592,11 +592,16 @@ class Queue:
         if -1000 < rc < 0:                        # bad ticket or argument
             _check(rc, "posit32_queue_poll/wait")
         del self._shapes[ticket]
-        return {"X": X, "status": res.status, "info": res.info, "factor": res.factor,
+        # a request that failed (status != 0) has no solution: X is None
+        return {"X": X if res.status == 0 else None, "status": res.status, "info": res.info,
+                "factor": res.factor,
                 "submit_s": res.submit_s, "start_s": res.start_s, "done_s": res.done_s}
 
     def poll(self, ticket: int):
-        """The result dict once the request is done, else None."""
+        """The result dict once the request is done, else None: X (the n x nrhs
+        solution; the unsolved B when info > 0; None when status != 0), status
+        (0 or a library error code), info, factor (a resident factor's handle
+        or 0) and the submit / start / done times."""
         return self._collect(ticket, lambda x, r: lib().posit32_queue_poll(self._h, ticket, x, r))
 
     def wait(self, ticket: int, timeout_s: float = -1.0):

@@ -18,9 +18,10 @@
 //     kMidShare of them are in the batch; the others go through the
 //     single-matrix routines, except that the new LU systems among them are
 //     factored together (launch_getrf_group: their panels in one cooperative
-//     launch per panel step, their trailing updates in one launch), so large
-//     systems in one batch share the device instead of queueing behind each
-//     other;
+//     launch per panel step, their trailing updates in one launch), and the
+//     large Cholesky systems run by turns on kSideStreams side streams, so
+//     large systems in one batch share the device instead of queueing behind
+//     each other;
 //   * overlap: a batch's host-to-device copies run on a copy stream while the
 //     previous batch computes on the compute stream; results come back on the
 //     compute stream and are copied out when its event completes;
@@ -56,6 +57,9 @@ constexpr int kSlots = 2;                    // batches in flight
 // a batch and run side by side; they join the batched launch only when at
 // least this many of them are in the batch.
 constexpr size_t kMidShare = 4;
+// Large Cholesky systems of a batch each go to one of these streams (by
+// turns), so that their latency-bound column steps overlap on the device.
+constexpr int kSideStreams = 4;
 
 size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
@@ -139,6 +143,8 @@ struct Slot {
   char* dev_meta = nullptr;                  // device: launch arrays
   size_t dev_meta_cap = 0;
   hipEvent_t ev_in = nullptr, ev_done = nullptr;
+  hipEvent_t ev_start = nullptr;             // compute stream: inputs and info ready
+  hipEvent_t ev_side[kSideStreams] = {};     // side stream k: its systems done
   bool busy = false;
 };
 
@@ -149,6 +155,7 @@ struct posit32_queue {
   p32::Tuning tune[2];                       // sub-panel tables: LU, Cholesky
   int device = 0;
   hipStream_t compute = nullptr, copy = nullptr;
+  hipStream_t side[kSideStreams] = {};       // large Cholesky systems (default priority)
   char* dev_pool = nullptr;
   Pool pool;
   std::chrono::steady_clock::time_point t0;
@@ -366,6 +373,32 @@ int start_batch(posit32_queue* q, Slot& s) {
                        (int32_t)large.size());
     rc = p32::launch_status();
   }
+  // the large Cholesky systems, by turns on the side streams, which first
+  // wait for everything queued on the compute stream so far (inputs, info
+  // zeroing); the compute stream waits for them before the results are
+  // copied out
+  int sides = 0;
+  {
+    size_t nchol = 0;
+    for (Req* r : large) nchol += r->kind == 1;
+    sides = (int)std::min(nchol, (size_t)kSideStreams);
+  }
+  if (!rc && sides > 0) {
+    rc = hip_code(hipEventRecord(s.ev_start, q->compute));
+    for (int k = 0; k < sides && !rc; ++k) rc = hip_code(hipStreamWaitEvent(q->side[k], s.ev_start, 0));
+    int turn = 0;
+    for (size_t i = 0; i < large.size() && !rc; ++i) {
+      Req* r = large[i];
+      if (r->kind != 1) continue;
+      hipStream_t st = q->side[turn++ % sides];
+      uint32_t* A = (uint32_t*)(pool + r->fac_off);
+      uint32_t* B = (uint32_t*)(pool + r->rhs_off);
+      int32_t* info = dinfo + sub + (int32_t)i;
+      if (!r->factor_in) rc = p32::launch_potrf(st, 0, r->n, q->cfg.nb, A, r->n, info);
+      if (!rc) rc = p32::launch_potrs(st, 0, r->n, r->nrhs, A, r->n, B, r->nrhs);
+    }
+    for (int k = 0; k < sides && !rc; ++k) rc = hip_code(hipEventRecord(s.ev_side[k], q->side[k]));
+  }
   // the new LU systems among them are factored together, up to
   // kGetrfGroupMax at a time (their panels share the per-column latency)
   std::vector<Req*> lu_new;
@@ -408,19 +441,8 @@ int start_batch(posit32_queue* q, Slot& s) {
     // right-hand sides in the ldb array (B is n x nrhs, row stride nrhs)
     rc = p32::launch_getrs_group(q->compute, c, n, nrhs, LU, ld, ipiv, B, nrhs);
   }
-  for (Req* r : large) {
-    if (rc) break;
-    uint32_t* A = (uint32_t*)(pool + r->fac_off);
-    uint32_t* B = (uint32_t*)(pool + r->rhs_off);
-    int32_t* info = dinfo + sub;
-    r->info = sub++;
-    if (r->kind == 0) {
-      continue;                                  // factored and solved above
-    } else {
-      if (!r->factor_in) rc = p32::launch_potrf(q->compute, 0, r->n, q->cfg.nb, A, r->n, info);
-      if (!rc) rc = p32::launch_potrs(q->compute, 0, r->n, r->nrhs, A, r->n, B, r->nrhs);
-    }
-  }
+  for (Req* r : large) r->info = sub++;           // LU above, Cholesky on the side streams
+  for (int k = 0; k < sides && !rc; ++k) rc = hip_code(hipStreamWaitEvent(q->compute, s.ev_side[k], 0));
   if (rc) return rc;
   // results: info array, then each solution
   rc = hip_code(hipMemcpyAsync(s.pin_out, s.dev_meta + info_off, rs.size() * 4, hipMemcpyDeviceToHost,
@@ -512,6 +534,7 @@ void worker_main(posit32_queue* q) {
         if (rc) {
           if (!q->fatal) q->fatal = rc;
           (void)hipStreamSynchronize(q->compute);
+          for (hipStream_t st : q->side) (void)hipStreamSynchronize(st);
           finish_batch(q, s, rc);
         } else {
           q->inflight.push_back(free_slot);
@@ -566,10 +589,15 @@ int posit32_queue_create(const posit32_queue_cfg* cfg, posit32_queue** out) {
   int rc = hip_code(hipGetDevice(&q->device));
   if (!rc) rc = hip_code(hipStreamCreateWithFlags(&q->compute, hipStreamNonBlocking));
   if (!rc) rc = hip_code(hipStreamCreateWithFlags(&q->copy, hipStreamNonBlocking));
+  for (int k = 0; k < kSideStreams && !rc; ++k)
+    rc = hip_code(hipStreamCreateWithFlags(&q->side[k], hipStreamNonBlocking));
   if (!rc) rc = hip_code(hipMalloc((void**)&q->dev_pool, (size_t)cfg->device_bytes));
   for (int i = 0; i < kSlots && !rc; ++i) {
     rc = hip_code(hipEventCreateWithFlags(&q->slots[i].ev_in, hipEventDisableTiming));
     if (!rc) rc = hip_code(hipEventCreateWithFlags(&q->slots[i].ev_done, hipEventDisableTiming));
+    if (!rc) rc = hip_code(hipEventCreateWithFlags(&q->slots[i].ev_start, hipEventDisableTiming));
+    for (int k = 0; k < kSideStreams && !rc; ++k)
+      rc = hip_code(hipEventCreateWithFlags(&q->slots[i].ev_side[k], hipEventDisableTiming));
   }
   if (rc) {
     posit32_queue_destroy(q.release());
@@ -700,10 +728,17 @@ int posit32_queue_destroy(posit32_queue* q) {
     if (s.dev_meta) (void)hipFree(s.dev_meta);
     if (s.ev_in) (void)hipEventDestroy(s.ev_in);
     if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+    if (s.ev_start) (void)hipEventDestroy(s.ev_start);
+    for (hipEvent_t e : s.ev_side)
+      if (e) (void)hipEventDestroy(e);
   }
+  for (hipStream_t st : q->side)
+    if (st) (void)hipStreamSynchronize(st);
   if (q->dev_pool) (void)hipFree(q->dev_pool);
   if (q->compute) (void)hipStreamDestroy(q->compute);
   if (q->copy) (void)hipStreamDestroy(q->copy);
+  for (hipStream_t st : q->side)
+    if (st) (void)hipStreamDestroy(st);
   delete q;
   return 0;
 }

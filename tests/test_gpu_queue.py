@@ -266,3 +266,42 @@ def test_queue_large_lu_burst_factored_together(P):
         if sizes[i] in (600, 768):
             LU, ipiv, _ = O.getrf(A, 256)
             assert np.array_equal(out["X"], O.getrs(LU, ipiv, B)), i
+
+
+def test_queue_large_chol_burst_on_side_streams(P):
+    """A burst of large Cholesky systems (520..1400, one not positive
+    definite, two solved with a resident factor) submitted at once: the
+    queue runs a batch's large Cholesky systems side by side on several
+    streams; every solution equals the system solved alone, and the
+    oracle's for one of them."""
+    rng = np.random.default_rng(32)
+    sizes = [1400, 520, 900, 610, 1100, 700, 530, 1250, 800, 560]
+    reqs = []
+    for i, n in enumerate(sizes):
+        A = _spd(rng, n)
+        if i == 4:
+            A[300, 300] = p32([-3.0])[0]                # fails at column 301
+        B = p32(rng.uniform(-1, 1, (n, int(rng.integers(1, 6)))))
+        reqs.append((A, B))
+    q = P.Queue(device_bytes=1 << 30, max_batch=64, nb=256, batch_max_n=512)
+    first = q.wait(q.submit(1, reqs[1][1], reqs[1][0], keep=True), 120.0)
+    tickets = [q.submit(1, B, A) for A, B in reqs]
+    again = [q.submit(1, reqs[1][1], factor=first["factor"]) for _ in range(2)]
+    outs = [q.wait(t, 300.0) for t in tickets]
+    outs_again = [q.wait(t, 300.0) for t in again]
+    st = q.stats()
+    q.release(first["factor"])
+    q.close()
+    assert st["batches"] < len(sizes) + 3                # several systems shared a batch
+    for i, ((A, B), out) in enumerate(zip(reqs, outs)):
+        assert out is not None and out["status"] == 0
+        X, info = _alone(P, 1, A, B)
+        assert out["info"] == info
+        assert (info > 0) == (i == 4)
+        assert np.array_equal(out["X"], X if info == 0 else B), i
+    X1, _ = _alone(P, 1, reqs[1][0], reqs[1][1])
+    assert np.array_equal(first["X"], X1)
+    for o in outs_again:
+        assert o["status"] == 0 and np.array_equal(o["X"], X1)
+    L, info = O.potrf(reqs[6][0], 256)
+    assert info == 0 and np.array_equal(outs[6]["X"], O.potrs(L, reqs[6][1]))

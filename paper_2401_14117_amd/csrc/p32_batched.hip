@@ -526,13 +526,14 @@ struct Batch {
 
 // KIND 0: LU, 1: Cholesky.  FACTOR / SOLVE select the phases; with both, a
 // failed factorisation (info > 0) skips the solve.
-// Everything is inlined into the kernel, with a register budget of four waves
-// per SIMD (128 VGPRs).  That spills 200-350 bytes per lane to scratch, but the
-// extra waves hide the latency of the unblocked steps' barriers and divisions:
-// on the 20,000-system batches 4 waves per SIMD run 23% faster than 2 (no
-// spills) and 6% faster than 3; 5 and 6 are no faster.
+// Everything is inlined into the kernel, with a register budget of six waves
+// per SIMD (80 VGPRs).  That spills to scratch, but the extra waves
+// hide the latency of the unblocked steps' barriers and divisions: on the
+// 20,000-system batches, 6 waves per SIMD run 2% (LU) and 5% (Cholesky)
+// faster than 4, which was itself 23% faster than 2 (no spills); 5 is between
+// them and 8 is several times slower (the spills dominate).
 #ifndef P32_BATCH_MIN_WAVES
-#define P32_BATCH_MIN_WAVES 4
+#define P32_BATCH_MIN_WAVES 6
 #endif
 template <int KIND, bool FACTOR, bool SOLVE>
 __global__ void __launch_bounds__(kBT, P32_BATCH_MIN_WAVES) vbatched_kernel(Batch bt) {
@@ -587,13 +588,13 @@ int launch_kernel(hipStream_t s, const Batch& bt) {
 
 // Built-in sub-panel widths per size bucket, measured on MI355X (the
 // autotuner replaces them per device): a width >= n runs small systems
-// unblocked, 16 suits the LU of orders 48-95 and 32 the larger systems.
+// unblocked, 32 suits the larger systems.
 Tuning default_tuning(int kind) {
   Tuning t{};
   t.buckets = 6;
   const int32_t max_n[6] = {23, 47, 95, 191, 383, 0x7FFFFFFF};
-  const int32_t lu[6] = {48, 48, 16, 32, 32, 32};
-  const int32_t chol[6] = {48, 48, 32, 32, 32, 32};
+  const int32_t lu[6] = {48, 48, 32, 32, 32, 32};
+  const int32_t chol[6] = {48, 64, 32, 32, 32, 32};
   for (int b = 0; b < 6; ++b) {
     t.max_n[b] = max_n[b];
     t.sub[b] = kind == 0 ? lu[b] : chol[b];

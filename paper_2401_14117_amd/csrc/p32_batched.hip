@@ -61,10 +61,16 @@ namespace {
 
 constexpr int kBT = NT;          // threads per workgroup (the tile routine needs NT)
 constexpr int kMaxSub = 64;      // widest sub-panel / sub-block
+// k-steps of a proven k-tile unrolled per loop iteration in the tile routine:
+// 2 is fastest at six waves per SIMD (fewer live registers than 4).  A build
+// that did not unroll that loop at all gave wrong results on some systems
+// (a code-generation fault whose cause was not isolated; every unrolled
+// build matches the oracle), so 1 is refused.
 #ifndef P32_BATCH_UNROLL
-#define P32_BATCH_UNROLL 4
+#define P32_BATCH_UNROLL 2
 #endif
-constexpr int kUnroll = P32_BATCH_UNROLL;   // k-steps unrolled in the tile routine
+constexpr int kUnroll = P32_BATCH_UNROLL;
+static_assert(kUnroll >= 2, "the tile routine's proven k-tile loop must be unrolled");
 constexpr uint32_t kMinus1 = 0xC0000000u;
 
 struct Shared {

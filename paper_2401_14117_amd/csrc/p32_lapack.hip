@@ -882,6 +882,53 @@ __global__ void apply_pivots_kernel(uint32_t* __restrict__ B, int64_t ldb, int64
   apply_pivots_body(B, ldb, n, nrhs, ipiv, reverse, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// The same interchanges with right-hand side q staged in LDS (n <=
+// kPivLdsMax; 8 bytes of LDS per row): the column and the pivot indices are
+// loaded by the whole workgroup, one thread makes the swaps in order on LDS
+// (a chain of LDS round trips instead of global-memory ones), and the column
+// is written back.
+constexpr int64_t kPivLdsMax = 8192;
+
+__device__ __forceinline__ void apply_pivots_lds_body(uint32_t* __restrict__ B, int64_t ldb, int64_t n,
+                                                      const int32_t* __restrict__ ipiv, int reverse, int64_t q,
+                                                      uint32_t* xs, int32_t* ps) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    xs[i] = B[i * ldb + q];
+    ps[i] = ipiv[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t c = reverse ? n - 1 - t : t;
+      const int64_t p = ps[c];
+      if (p != c) {
+        const uint32_t x = xs[c];
+        xs[c] = xs[p];
+        xs[p] = x;
+      }
+    }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) B[i * ldb + q] = xs[i];
+}
+
+__global__ void __launch_bounds__(256)
+apply_pivots_lds_kernel(uint32_t* __restrict__ B, int64_t ldb, int64_t n, const int32_t* __restrict__ ipiv,
+                        int reverse) {
+  extern __shared__ uint32_t piv_lds[];
+  apply_pivots_lds_body(B, ldb, n, ipiv, reverse, blockIdx.x, piv_lds, reinterpret_cast<int32_t*>(piv_lds + n));
+}
+
+// interchanges of nrhs right-hand sides of an n-row system
+static void launch_pivots(hipStream_t s, uint32_t* B, int64_t ldb, int64_t n, int64_t nrhs, const int32_t* ipiv,
+                          int reverse) {
+  if (n <= kPivLdsMax)
+    hipLaunchKernelGGL(apply_pivots_lds_kernel, dim3((unsigned)nrhs), dim3(256), (size_t)n * 8, s, B, ldb, n,
+                       ipiv, reverse);
+  else
+    hipLaunchKernelGGL(apply_pivots_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, B, ldb, n, nrhs,
+                       ipiv, reverse);
+}
+
 // ---- getrs on several systems at once -------------------------------------------
 // The forward and backward substitutions of up to kGroupMax systems advance
 // block by block together: at block step b, one launch solves the b-th
@@ -910,6 +957,16 @@ __global__ void apply_pivots_group_kernel(SolveGroup g) {
   const int sys = blockIdx.y;
   apply_pivots_body(g.B[sys], g.ldb[sys], g.n[sys], g.nrhs[sys], g.ipiv[sys], 0,
                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// right-hand side blockIdx.x of system blockIdx.y, staged in LDS (every n <= kPivLdsMax)
+__global__ void __launch_bounds__(256) apply_pivots_group_lds_kernel(SolveGroup g) {
+  extern __shared__ uint32_t piv_lds[];
+  const int sys = blockIdx.y;
+  const int64_t n = g.n[sys];
+  if ((int64_t)blockIdx.x >= g.nrhs[sys]) return;
+  apply_pivots_lds_body(g.B[sys], g.ldb[sys], n, g.ipiv[sys], 0, blockIdx.x, piv_lds,
+                        reinterpret_cast<int32_t*>(piv_lds + n));
 }
 
 template <int kind>
@@ -1313,15 +1370,14 @@ int launch_getrf_noalloc(hipStream_t s, int64_t n, int64_t nb, uint32_t* A, int6
 int launch_getrs(hipStream_t s, int trans, int64_t n, int64_t nrhs, const uint32_t* LU, int64_t lda,
                  const int32_t* ipiv, uint32_t* B, int64_t ldb) {
   if (n == 0 || nrhs == 0) return 0;
-  const dim3 pgrid((unsigned)((nrhs + 63) / 64)), pblock(64);
   if (trans) {
     int rc = trsv(s, LU, lda, n, B, ldb, nrhs, 4);
     if (rc == 0) rc = trsv(s, LU, lda, n, B, ldb, nrhs, 5);
     if (rc != 0) return rc;
-    hipLaunchKernelGGL(apply_pivots_kernel, pgrid, pblock, 0, s, B, ldb, n, nrhs, ipiv, 1);
+    launch_pivots(s, B, ldb, n, nrhs, ipiv, 1);
     return launch_status();
   }
-  hipLaunchKernelGGL(apply_pivots_kernel, pgrid, pblock, 0, s, B, ldb, n, nrhs, ipiv, 0);
+  launch_pivots(s, B, ldb, n, nrhs, ipiv, 0);
   int rc = trsv(s, LU, lda, n, B, ldb, nrhs, 0);
   if (rc != 0) return rc;
   return trsv(s, LU, lda, n, B, ldb, nrhs, 1);
@@ -1439,8 +1495,12 @@ int launch_getrs_group(hipStream_t s, int count, const int64_t* n, const int64_t
   }
   if (g.count == 0) return 0;
   if (rmax > 65535) return -1;                   // one diagonal workgroup per right-hand side in y
-  hipLaunchKernelGGL(apply_pivots_group_kernel, dim3((unsigned)((rmax + 63) / 64), (unsigned)g.count), dim3(64),
-                     0, s, g);
+  if (nmax <= kPivLdsMax)
+    hipLaunchKernelGGL(apply_pivots_group_lds_kernel, dim3((unsigned)rmax, (unsigned)g.count), dim3(256),
+                       (size_t)nmax * 8, s, g);
+  else
+    hipLaunchKernelGGL(apply_pivots_group_kernel, dim3((unsigned)((rmax + 63) / 64), (unsigned)g.count),
+                       dim3(64), 0, s, g);
   const int64_t nblk = (nmax + kTrsvBlock - 1) / kTrsvBlock;
   const unsigned gy = (unsigned)(rmax < 65535 ? rmax : 65535);
   const unsigned gx_upd = (unsigned)((nmax + kTrsvBlock - 1) / kTrsvBlock);

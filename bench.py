@@ -292,11 +292,12 @@ def run_solve_bench(name: str, args, dev) -> dict:
 def run_batch_bench(name: str, args, dev) -> dict:
     """batch_lu / batch_chol: the variable-size batched workload -- count
     systems (n log-uniform in [16, 512], nrhs in [1, 16]) factored and solved
-    by one persistent launch (posit32_gesv_vbatched / posit32_posv_vbatched).
-    One step = the whole batch, inputs resident in HBM (restored between steps
-    outside the timed region).  Beside it: the same library's single-matrix
-    calls, one system at a time, on a random sample of the batch (their
-    results are also compared with the batched ones bit for bit)."""
+    by one launch of one workgroup per system (posit32_gesv_vbatched /
+    posit32_posv_vbatched).  One step = the whole batch, inputs resident in
+    HBM (restored between steps outside the timed region).  Beside it: the
+    same library's single-matrix calls, one system at a time, on a random
+    sample of the batch (their results are also compared with the batched
+    ones bit for bit)."""
     import torch
     from paper_2401_14117_amd import posit32
     from paper_2401_14117_amd import workloads as W
@@ -480,7 +481,7 @@ def _batch_result(name, kind, count, kms, pops, info, setup_s, single, cpu, args
                    "nrhs": "1..16", "nb": args.nb, "factor_gpops": round(pops / (kms * 1e-3) / 1e9, 1),
                    "info_nonzero": int(np.count_nonzero(info)), "setup_s": round(setup_s, 1),
                    "sub_panel_tuning": _tuning_info(kind),
-                   "launch": "one persistent kernel captured in a hipGraph; each step is a replay",
+                   "launch": "one kernel (a workgroup per system) captured in a hipGraph; each step is a replay",
                    "graph_bit_identical_to_eager": graph_same, "one_at_a_time": single},
         "roofline": _batch_roofline(kind, kms, pops),
         "cpu_baseline": cpu,
@@ -690,7 +691,7 @@ def run_cpu_single_thread(budget_s: float) -> dict:
 
 def run_extras(args, dev) -> dict:
     """The other two clauses of the metric, measured in the same run: the
-    20,000-system batched factor + solve (one persistent launch, replayed
+    20,000-system batched factor + solve (one launch, replayed
     from a hipGraph) for LU and Cholesky, and the LU request queue under
     Poisson arrivals at one rate with the same requests one at a time."""
     import argparse as _ap

@@ -261,8 +261,9 @@ int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32
 
 /*
  * Variable-size batches of the factorisations and solves above: count
- * independent systems in one persistent launch (many small systems, the
- * sizes of the paper's LU and Cholesky study, Section 5, in large numbers).
+ * independent systems in one launch of one workgroup per system (many small
+ * systems, the sizes of the paper's LU and Cholesky study, Section 5, in
+ * large numbers).
  * Matrix i is factored and solved exactly as the single-matrix call with the
  * same nb would do it, bit for bit.
  *

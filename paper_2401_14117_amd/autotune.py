@@ -1,9 +1,9 @@
 """Autotuner of the batched factorisations: the sub-panel width per size bucket.
 
-The persistent batched kernels (posit32_vbatched) factor every panel in
+The batched kernels (posit32_vbatched) factor every panel in
 sub-panels of `sub` columns: inside a sub-panel the unblocked pivot search,
 division and rank-1 updates; outside it fused-update chains on the Rgemm tile
-routine; the solves work in blocks of `sub` rows.  The width regroups the work
+routine; the solves work in blocks of 64 rows.  The width regroups the work
 without changing the order in which any element receives its updates, so
 every width gives the same bits -- it only moves time between the
 latency-bound unblocked steps and the throughput-bound tiles, and the best

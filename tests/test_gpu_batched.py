@@ -329,3 +329,37 @@ def test_vbatched_graph_replay(P):
         for i in range(len(sizes)):
             assert np.array_equal(from_dev(As[i]), eA[i]) and np.array_equal(from_dev(Bs[i]), eB[i])
         assert np.array_equal(vb.info.cpu().numpy(), einfo)
+
+
+@pytest.mark.parametrize("kind,count", [("lu", 48), ("chol", 24)])
+def test_vbatched_workload_sample(P, kind, count):
+    """Systems of the batched workload itself (its size law and matrix recipe)
+    with 48 <= n <= 256, where every factorisation runs blocked updates,
+    batched together and each checked against the oracle bit for bit."""
+    from paper_2401_14117_amd import workloads as W
+    n, nrhs = W.batch_sizes(20000)
+    pick = np.nonzero((n >= 48) & (n <= 256))[0][:count]
+    mats, rhss = [], []
+    for i in pick:
+        _, A, B = next(W.batch_matrices(kind, n, nrhs, start=int(i), stop=int(i) + 1))
+        mats.append(p32(A))
+        rhss.append(p32(B))
+    order = sorted(range(count), key=lambda j: -mats[j].shape[0])
+    mats = [mats[j] for j in order]
+    rhss = [rhss[j] for j in order]
+    if kind == "lu":
+        gA, gpiv, ginfo, gB = _run_gesv(P, mats, rhss, 256)
+    else:
+        gA, ginfo, gB = _run_posv(P, mats, rhss, 256)
+    for j, A in enumerate(mats):
+        if kind == "lu":
+            F, ipiv, info = O.getrf(A, 256)
+            assert np.array_equal(gpiv[j], ipiv), j
+            assert np.array_equal(gA[j], F), (A.shape, _diff(gA[j], F))
+            X = O.getrs(F, ipiv, rhss[j])
+        else:
+            F, info = O.potrf(A, 256)
+            assert np.array_equal(np.tril(gA[j]), np.tril(F)), (A.shape, _diff(np.tril(gA[j]), np.tril(F)))
+            X = O.potrs(F, rhss[j])
+        assert ginfo[j] == info == 0, (A.shape, ginfo[j], info)
+        assert np.array_equal(gB[j], X), (A.shape, _diff(gB[j], X))

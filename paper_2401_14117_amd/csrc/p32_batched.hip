@@ -594,8 +594,8 @@ Tuning default_tuning(int kind) {
   Tuning t{};
   t.buckets = 6;
   const int32_t max_n[6] = {23, 47, 95, 191, 383, 0x7FFFFFFF};
-  const int32_t lu[6] = {48, 48, 32, 32, 32, 32};
-  const int32_t chol[6] = {48, 48, 32, 32, 32, 32};
+  const int32_t lu[6] = {48, 64, 32, 32, 32, 32};
+  const int32_t chol[6] = {64, 64, 32, 32, 32, 32};
   for (int b = 0; b < 6; ++b) {
     t.max_n[b] = max_n[b];
     t.sub[b] = kind == 0 ? lu[b] : chol[b];

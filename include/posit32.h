@@ -267,7 +267,9 @@ int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32
  * Matrix i is factored and solved exactly as the single-matrix call with the
  * same nb would do it, bit for bit.
  *
- *   count        number of systems, >= 0.
+ *   count        number of systems, 0 <= count <= P32_VBATCH_MAX_COUNT (one
+ *                workgroup of 256 threads per system, and a launch counts its
+ *                work-items in 32 bits).
  *   max_n        host-side bound, 0 <= n[i] <= max_n <= 2^24 - 2 (a matrix
  *                with a larger n[i] is rejected through its info[i]).
  *   nb           block size, 1 <= nb <= 256.
@@ -287,12 +289,14 @@ int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32
  *                -6 null B[i] with n[i], nrhs[i] > 0, -7 bad ldb[i].
  * posit32_gesv_vbatched / posit32_posv_vbatched factor and solve in the same
  * launch; a system whose factorisation reports info > 0 is not solved.
- * Workgroups take the systems round-robin (system i goes to workgroup
- * i mod G), so a batch ordered by decreasing n balances best.  The calls
- * allocate nothing and launch one kernel (they can be captured in a graph).
- * Systems must not share memory.  Errors: -2 count < 0, -3 bad max_n,
- * -4 bad nb, -5 a null array argument with count > 0.
+ * System i runs in workgroup i, and workgroups start in index order as
+ * earlier ones retire, so a batch ordered by decreasing n balances best.  The
+ * calls allocate nothing and launch one kernel (they can be captured in a
+ * graph).  Systems must not share memory.  Errors: -2 count outside
+ * [0, P32_VBATCH_MAX_COUNT], -3 bad max_n, -4 bad nb, -5 a null array
+ * argument with count > 0.
  */
+#define P32_VBATCH_MAX_COUNT 16777215
 int posit32_getrf_vbatched(void* stream, int32_t count, int32_t max_n, int64_t nb, const int32_t* n,
                            posit32_t* const* A, const int64_t* lda, int32_t* const* ipiv,
                            int32_t* info);

@@ -201,7 +201,7 @@ int posit32_potrs(void* stream, int uplo, int64_t n, int64_t nrhs, const posit32
 
 static int vb_common(int32_t count, int32_t max_n, const int32_t* n, posit32_t* const* A,
                      const int64_t* lda, int32_t* info) {
-  if (count < 0) return -2;
+  if (count < 0 || count > P32_VBATCH_MAX_COUNT) return -2;
   if (max_n < 0 || max_n > 0xFFFFFE) return -3;
   if (count > 0 && (n == nullptr || A == nullptr || lda == nullptr || info == nullptr)) return -5;
   return 0;

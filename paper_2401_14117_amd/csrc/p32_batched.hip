@@ -608,6 +608,7 @@ int launch_vbatched(hipStream_t s, int kind, bool factor, bool solve, int32_t co
                     int32_t* const* ipiv, const int32_t* nrhs, uint32_t* const* B, const int64_t* ldb,
                     int32_t* info, const Tuning* tune) {
   if (count == 0) return 0;
+  if (count < 0 || (int64_t)count * kBT > 0xFFFFFFFFll) return -2;   // grid of count * 256 work-items
   Batch bt{tune != nullptr ? *tune : default_tuning(kind), count, max_n, (int32_t)nb, n, A, lda, ipiv, nrhs,
            B, ldb, info};
   if (kind == 0) {

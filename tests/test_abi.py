@@ -151,6 +151,8 @@ def test_factorisation_argument_errors(L):
 def test_vbatched_argument_errors(L):
     # count, max_n, nb and null arrays are checked on the host; count = 0 is a no-op
     assert L.posit32_getrf_vbatched(None, -1, 8, 256, 8, 8, 8, 8, 8) == -2
+    assert L.posit32_getrf_vbatched(None, 1 << 24, 8, 256, 8, 8, 8, 8, 8) == -2   # > P32_VBATCH_MAX_COUNT
+    assert L.posit32_gesv_vbatched(None, (1 << 24) - 1, 1 << 24, 256, 8, 8, 8, 8, 8, 8, 8, 8) == -3
     assert L.posit32_getrf_vbatched(None, 1, -1, 256, 8, 8, 8, 8, 8) == -3
     assert L.posit32_getrf_vbatched(None, 1, 1 << 24, 256, 8, 8, 8, 8, 8) == -3
     assert L.posit32_getrf_vbatched(None, 1, 8, 0, 8, 8, 8, 8, 8) == -4

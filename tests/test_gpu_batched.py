@@ -363,3 +363,26 @@ def test_vbatched_workload_sample(P, kind, count):
             X = O.potrs(F, rhss[j])
         assert ginfo[j] == info == 0, (A.shape, ginfo[j], info)
         assert np.array_equal(gB[j], X), (A.shape, _diff(gB[j], X))
+
+
+def test_vbatched_large_batch_sample(P):
+    """A batch of 4,000 systems, many more than the device holds resident at
+    once, so most workgroups start only after others have retired; systems
+    sampled across the whole batch (the last ones included) equal the
+    oracle bit for bit."""
+    rng = np.random.default_rng(21)
+    count = 4000
+    sizes = sorted(np.round(np.exp(rng.uniform(np.log(16), np.log(96), count))).astype(int),
+                   reverse=True)
+    mats = [_lu_matrix(rng, int(n)) for n in sizes]
+    rhss = [p32(rng.uniform(-1, 1, (int(n), int(rng.integers(1, 5))))) for n in sizes]
+    gA, gpiv, ginfo, gB = _run_gesv(P, mats, rhss, 256)
+    assert ginfo.shape == (count,)
+    picks = sorted(set(np.linspace(0, count - 1, 30).astype(int).tolist()) | {count - 2, count - 1})
+    for i in picks:
+        LU, ipiv, info = O.getrf(mats[i], 256)
+        assert ginfo[i] == info, (i, ginfo[i], info)
+        assert np.array_equal(gpiv[i], ipiv), i
+        assert np.array_equal(gA[i], LU), (i, sizes[i], _diff(gA[i], LU))
+        X = O.getrs(LU, ipiv, rhss[i])
+        assert np.array_equal(gB[i], X), (i, sizes[i], _diff(gB[i], X))

@@ -276,7 +276,7 @@ int launch_batch(posit32_queue* q, Slot& s, const std::vector<Req*>& group, int 
 // Stage, copy and launch one batch into slot s (without the lock).
 int start_batch(posit32_queue* q, Slot& s) {
   std::vector<Req*>& rs = s.reqs;
-  // largest systems first: the batched kernel hands systems out round-robin
+  // largest systems first: the batched kernel's workgroups start in system order
   std::stable_sort(rs.begin(), rs.end(), [](const Req* a, const Req* b) { return a->n > b->n; });
   const int64_t small_max = q->cfg.batch_max_n, mid_min = small_max / 2;
   size_t mid = 0;
